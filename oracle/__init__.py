@@ -1,0 +1,213 @@
+"""Sequential CPU oracle for the VSBPP placement heuristics (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  The oracle checks the HIP path and shares no code
+with it.  Only the test-suite, the smoke check and the benchmark's CPU-baseline
+leg may import this package; the product path never does.
+
+The C source (``vsbpp_oracle.c``) states each step of the paper's method
+(Section 1 for FF/BF/WF, Section 6.3 for the first heuristic, Section 6.4 for
+the second) in plain sequential code.  This module only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vsbpp_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+FF, BF, WF, H1, H2 = 0, 1, 2, 3, 4
+HEURISTICS = {"FF": FF, "BF": BF, "WF": WF, "H1": H1, "H2": H2}
+TYPE_SMALLEST_FIT, TYPE_LARGEST = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+    ):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+             "-o", tmp, _SRC]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64),
+        ("s1", ctypes.c_int32),
+        ("s2", ctypes.c_int32),
+        ("type_rule", ctypes.c_int32),
+        ("force_crit", ctypes.c_int32),
+        ("order", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("packers", ctypes.c_int64),
+        ("perm_packings", ctypes.c_int64),
+        ("placements", ctypes.c_int64),
+        ("bin_tests", ctypes.c_int64),
+        ("live_tests", ctypes.c_int64),
+        ("new_bins", ctypes.c_int64),
+        ("divisions", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_stream_key.restype = ctypes.c_uint64
+        L.orc_stream_key.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_criterion.restype = ctypes.c_int32
+        L.orc_criterion.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_perm.restype = ctypes.c_int32
+        L.orc_perm.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]
+        L.orc_pack.restype = ctypes.c_int32
+        L.orc_pack.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(_Opts), i32p, i32p, i64p,
+                               ctypes.POINTER(_Stats)]
+        L.orc_pack_packer.restype = ctypes.c_int32
+        L.orc_pack_packer.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32, i32p,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      i32p, i32p, i64p]
+        for name in ("orc_lb_cap", "orc_lb_big", "orc_opt_partitions", "orc_opt_subset_dp"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_int64
+            f.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32]
+        L.orc_lb_sum.restype = ctypes.c_int64
+        L.orc_lb_sum.argtypes = [i32p, ctypes.c_int32]
+        _lib = L
+    return _lib
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+@dataclass
+class Packing:
+    assignment: np.ndarray   # int32[m]: bin id per item
+    bin_types: np.ndarray    # int32[nbins]: type index per bin (0 = B_1)
+    nbins: int
+    cost: int
+    stats: dict
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code}")
+        self.code = code
+
+
+def splitmix64(seed: int, k: int) -> int:
+    return int(lib().orc_splitmix64(seed & (2**64 - 1), k & (2**64 - 1)))
+
+
+def stream_key(seed: int, stream: int) -> int:
+    return int(lib().orc_stream_key(seed & (2**64 - 1), stream))
+
+
+def criterion(key: int, counter: int) -> int:
+    return int(lib().orc_criterion(key & (2**64 - 1), counter))
+
+
+def perm(seed: int, m: int) -> np.ndarray:
+    """The Rule-1 permutation: entry q is the item at position q."""
+    L = lib()
+    return np.array([L.orc_perm(seed & (2**64 - 1), m, q) for q in range(m)], dtype=np.int32)
+
+
+def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
+         type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
+         order=None) -> Packing:
+    w = _i32(weights)
+    c = _i32(caps)
+    m = int(w.size)
+    assign = np.zeros(max(m, 1), dtype=np.int32)
+    types = np.zeros(max(m, 1), dtype=np.int32)
+    cost = ctypes.c_int64(0)
+    st = _Stats()
+    o = _Opts(seed & (2**64 - 1), s1, s2, type_rule, force_crit, None)
+    order_arr = None
+    if order is not None:
+        order_arr = _i32(order)
+        o.order = _p32(order_arr)
+    if isinstance(heuristic, str):
+        heuristic = HEURISTICS[heuristic]
+    rc = lib().orc_pack(_p32(w), m, _p32(c), int(c.size), int(heuristic), ctypes.byref(o),
+                        _p32(assign), _p32(types), ctypes.byref(cost), ctypes.byref(st))
+    if rc < 0:
+        raise OracleError(rc)
+    stats = {f: int(getattr(st, f)) for f, _ in _Stats._fields_}
+    return Packing(assign[:m].copy(), types[:rc].copy(), int(rc), int(cost.value), stats)
+
+
+def pack_packer(weights, caps, crit, *, rule2: bool, rule5: bool,
+                type_rule: int = TYPE_SMALLEST_FIT) -> Packing:
+    """One hybrid-P-system packer with explicit per-placement criteria."""
+    w = _i32(weights)
+    c = _i32(caps)
+    cr = _i32(crit)
+    m = int(w.size)
+    assign = np.zeros(max(m, 1), dtype=np.int32)
+    types = np.zeros(max(m, 1), dtype=np.int32)
+    cost = ctypes.c_int64(0)
+    rc = lib().orc_pack_packer(_p32(w), m, _p32(c), int(c.size), _p32(cr), int(rule2),
+                               int(rule5), type_rule, _p32(assign), _p32(types),
+                               ctypes.byref(cost))
+    if rc < 0:
+        raise OracleError(rc)
+    return Packing(assign[:m].copy(), types[:rc].copy(), int(rc), int(cost.value), {})
+
+
+def lb_sum(weights) -> int:
+    w = _i32(weights)
+    return int(lib().orc_lb_sum(_p32(w), int(w.size)))
+
+
+def lb_cap(weights, caps) -> int:
+    w, c = _i32(weights), _i32(caps)
+    return int(lib().orc_lb_cap(_p32(w), int(w.size), _p32(c), int(c.size)))
+
+
+def lb_big(weights, caps) -> int:
+    w, c = _i32(weights), _i32(caps)
+    return int(lib().orc_lb_big(_p32(w), int(w.size), _p32(c), int(c.size)))
+
+
+def lower_bound(weights, caps) -> int:
+    """LB = max(LB_cap, LB_big), the denominator of the cost/LB metric."""
+    return max(lb_cap(weights, caps), lb_big(weights, caps))
+
+
+def opt_partitions(weights, caps) -> int:
+    w, c = _i32(weights), _i32(caps)
+    return int(lib().orc_opt_partitions(_p32(w), int(w.size), _p32(c), int(c.size)))
+
+
+def opt_subset_dp(weights, caps) -> int:
+    w, c = _i32(weights), _i32(caps)
+    return int(lib().orc_opt_subset_dp(_p32(w), int(w.size), _p32(c), int(c.size)))

@@ -1,0 +1,568 @@
+/*
+ * Sequential CPU oracle for the VSBPP placement heuristics (Alenezi et al.).
+ *
+ * TEST INFRASTRUCTURE ONLY: it checks the HIP path and shares no code with
+ * it.  Every function is the plain, slow statement of what the paper (and the
+ * readings listed with it) computes; there is no blocking, fusion or pruning.
+ *
+ * Citations name the paper's sections, rules and tables.
+ */
+#include "vsbpp_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------- */
+/* Counter-based generator.                                                */
+/* ---------------------------------------------------------------------- */
+
+/* SplitMix64 as published by Steele, Lea & Flood (OOPSLA 2014): the state
+ * advances by the golden-gamma 0x9e3779b97f4a7c15 and each output is the
+ * state passed through the 64-bit finaliser (shift-xor 30, multiply,
+ * shift-xor 27, multiply, shift-xor 31).  Output k uses state seed+(k+1)*g. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1u) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+uint64_t orc_stream_key(uint64_t seed, uint64_t stream) {
+  return orc_splitmix64(seed, stream);
+}
+
+/* Rule 3 (Section 6.3): the item leaving its sublist is tagged with FF, BF
+ * or WF "with equal probabilities".  The draw maps the high 32 bits x of a
+ * generator output to floor(3x / 2^32) (multiply-shift range reduction). */
+int32_t orc_criterion(uint64_t stream_key, uint64_t counter) {
+  uint64_t hi = orc_splitmix64(stream_key, counter) >> 32;
+  return (int32_t)((hi * 3u) >> 32);
+}
+
+/* purposes of the generator streams */
+#define STREAM_RULE1 1u
+#define STREAM_H1 2u
+#define STREAM_H2 3u
+
+/* Rule 1 (Section 6.2/6.3 step 1) distributes the items "randomly" into the
+ * sublists.  Reading: a keyed pseudo-random permutation pi of [0,m) assigns
+ * item pi(q) to position q, and sublists are consecutive runs of positions.
+ * pi is a 4-round balanced Feistel network over 2h bits (2^(2h) >= m) whose
+ * round function is the generator, restricted to [0,m) by cycle walking
+ * (Black & Rogaway, "Ciphers with arbitrary finite domains", CT-RSA 2002). */
+static uint32_t feistel(uint64_t key, uint32_t h, uint32_t x) {
+  uint32_t mask = (1u << h) - 1u;
+  uint32_t left = x >> h, right = x & mask;
+  for (uint32_t r = 0; r < 4; ++r) {
+    uint32_t f = (uint32_t)(orc_splitmix64(key, ((uint64_t)r << 32) | right)) & mask;
+    uint32_t nl = right;
+    right = left ^ f;
+    left = nl;
+  }
+  return (left << h) | right;
+}
+
+int32_t orc_perm(uint64_t seed, int32_t m, int32_t q) {
+  if (m <= 1) return 0;
+  uint32_t bits = 0;
+  while ((1ull << bits) < (uint64_t)m) ++bits;
+  uint32_t h = (bits + 1) / 2;
+  uint64_t key = orc_stream_key(seed, STREAM_RULE1);
+  uint32_t y = feistel(key, h, (uint32_t)q);
+  while (y >= (uint32_t)m) y = feistel(key, h, y);
+  return (int32_t)y;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Packer: an ordered list of bins (creation order = bin index).           */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t type;
+  int64_t load;
+  int32_t divided;
+} obin;
+
+typedef struct {
+  obin* b;
+  int32_t nb, capn;
+} opacker;
+
+static void pk_init(opacker* p) { p->b = NULL; p->nb = 0; p->capn = 0; }
+static void pk_free(opacker* p) { free(p->b); pk_init(p); }
+static void pk_push(opacker* p, int32_t type) {
+  if (p->nb == p->capn) {
+    p->capn = p->capn ? 2 * p->capn : 16;
+    p->b = (obin*)realloc(p->b, sizeof(obin) * (size_t)p->capn);
+  }
+  p->b[p->nb].type = type;
+  p->b[p->nb].load = 0;
+  p->b[p->nb].divided = 0;
+  p->nb++;
+}
+
+/* Type of a bin opened when no open bin can take the item.  The paper says
+ * extra rules are needed to choose among bin types (Section 1) but gives
+ * none.  SMALLEST_FIT takes the smallest capacity >= w; LARGEST takes B_1. */
+static int32_t open_type(const int32_t* caps, int32_t n, int32_t w, int32_t rule) {
+  if (rule == ORC_TYPE_LARGEST) return 0;
+  for (int32_t k = n - 1; k >= 0; --k)
+    if (caps[k] >= w) return k;
+  return 0; /* unreachable for valid input: w <= B_1 */
+}
+
+/* Rule 4 (Section 6.3) with the FF/BF/WF choices of Section 1.
+ * Candidate set: bins whose load plus w stays within capacity.
+ *   FF: the candidate with the lowest index.
+ *   BF: least room left after placing; ties -> lowest index.
+ *   WF: most room left after placing; ties -> lowest index.
+ * No candidate: open a bin (type per open_type).
+ * Rule 5 (when enabled): a bin whose load reaches half its capacity and that
+ * has not divided yet divides once, adding an empty bin of its type.
+ * `suffix_min` is the smallest weight among this item and all later items of
+ * the same packer; it only feeds the work counters. */
+static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
+                     int32_t crit, int32_t rule5, int32_t type_rule,
+                     int64_t suffix_min, orc_stats* st) {
+  int32_t best = -1;
+  int64_t best_after = 0;
+  for (int32_t b = 0; b < p->nb; ++b) {
+    int64_t room = (int64_t)caps[p->b[b].type] - p->b[b].load;
+    if (st) {
+      st->bin_tests++;
+      if (room >= suffix_min) st->live_tests++;
+    }
+    if (room < w) continue;
+    int64_t after = room - w;
+    if (crit == ORC_FF) {
+      best = b;
+      break;
+    }
+    if (best < 0 || (crit == ORC_BF ? after < best_after : after > best_after)) {
+      best = b;
+      best_after = after;
+    }
+  }
+  if (best < 0) {
+    pk_push(p, open_type(caps, n, w, type_rule));
+    best = p->nb - 1;
+    if (st) st->new_bins++;
+  }
+  obin* bb = &p->b[best];
+  bb->load += w;
+  if (rule5 && !bb->divided && 2 * bb->load >= (int64_t)caps[bb->type]) {
+    int32_t t = bb->type;
+    bb->divided = 1;
+    pk_push(p, t); /* may move p->b */
+    if (st) st->divisions++;
+  }
+  if (st) st->placements++;
+  return best;
+}
+
+/* Canonical output of one packer: bins with load > 0 keep creation order and
+ * get consecutive ids starting at `base`; empty bins (Rule 2 / Rule 5 bins
+ * that never received an item) are not used and cost nothing. */
+static int32_t emit_packer(const opacker* p, const int32_t* caps, const int32_t* items,
+                           const int32_t* local, int32_t k, int32_t base,
+                           int32_t* assign, int32_t* types, int64_t* cost) {
+  int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)(p->nb ? p->nb : 1));
+  int32_t used = 0;
+  for (int32_t b = 0; b < p->nb; ++b) {
+    if (p->b[b].load > 0) {
+      rank[b] = used;
+      types[base + used] = p->b[b].type;
+      *cost += caps[p->b[b].type];
+      used++;
+    } else {
+      rank[b] = -1;
+    }
+  }
+  for (int32_t t = 0; t < k; ++t) assign[items[t]] = base + rank[local[t]];
+  free(rank);
+  return used;
+}
+
+static int64_t packer_cost(const opacker* p, const int32_t* caps) {
+  int64_t c = 0;
+  for (int32_t b = 0; b < p->nb; ++b)
+    if (p->b[b].load > 0) c += caps[p->b[b].type];
+  return c;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Validation.                                                             */
+/* ---------------------------------------------------------------------- */
+
+static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                        int32_t heuristic, const orc_opts* o) {
+  if (!w || !caps) return ORC_E_NULL;
+  if (m < 1 || n < 1 || n > 16) return ORC_E_SIZE;
+  for (int32_t k = 0; k < n; ++k) {
+    if (caps[k] <= 0) return ORC_E_CAPS;
+    if (k > 0 && caps[k] >= caps[k - 1]) return ORC_E_CAPS;
+  }
+  for (int32_t j = 0; j < m; ++j)
+    if (w[j] < 1 || w[j] > caps[0]) return ORC_E_WEIGHT;
+  if (heuristic < ORC_FF || heuristic > ORC_H2) return ORC_E_HEURISTIC;
+  if (o) {
+    if (o->s1 < 1 || o->s2 < 1 || o->s2 > 6) return ORC_E_OPTION;
+    if (o->type_rule != ORC_TYPE_SMALLEST_FIT && o->type_rule != ORC_TYPE_LARGEST)
+      return ORC_E_OPTION;
+    if (o->force_crit < -1 || o->force_crit > ORC_WF) return ORC_E_OPTION;
+    if (o->order) {
+      /* must be a permutation of [0,m) */
+      char* seen = (char*)calloc((size_t)m, 1);
+      for (int32_t q = 0; q < m; ++q) {
+        int32_t j = o->order[q];
+        if (j < 0 || j >= m || seen[j]) { free(seen); return ORC_E_OPTION; }
+        seen[j] = 1;
+      }
+      free(seen);
+    }
+  }
+  return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Heuristics.                                                             */
+/* ---------------------------------------------------------------------- */
+
+static int32_t item_at(const orc_opts* o, int32_t m, int32_t q, int32_t heuristic) {
+  if (o->order) return o->order[q];
+  if (heuristic == ORC_H1 || heuristic == ORC_H2) return orc_perm(o->seed, m, q);
+  return q; /* plain heuristics: input order */
+}
+
+/* Plain FF/BF/WF (Section 1): one packer over the whole list, starting with
+ * no bins, one fixed criterion, no Rule 2 and no Rule 5. */
+static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                         int32_t crit, const orc_opts* o, int32_t* assign,
+                         int32_t* types, int64_t* cost, orc_stats* st) {
+  int32_t* items = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int64_t* smin = (int64_t*)malloc(sizeof(int64_t) * (size_t)m);
+  for (int32_t q = 0; q < m; ++q) items[q] = item_at(o, m, q, crit);
+  for (int32_t q = m - 1; q >= 0; --q) {
+    int64_t v = w[items[q]];
+    smin[q] = (q == m - 1 || v < smin[q + 1]) ? v : smin[q + 1];
+  }
+  opacker p;
+  pk_init(&p);
+  for (int32_t q = 0; q < m; ++q)
+    local[q] = place(&p, caps, n, w[items[q]], crit, 0, o->type_rule, smin[q], st);
+  *cost = 0;
+  int32_t nb = emit_packer(&p, caps, items, local, m, 0, assign, types, cost);
+  if (st) st->packers += 1;
+  pk_free(&p);
+  free(items);
+  free(local);
+  free(smin);
+  return nb;
+}
+
+/* First heuristic (Section 6.3).  Sublist I holds positions
+ * [I*s1, min((I+1)*s1, m)); every sublist is its own packer that starts with
+ * one empty bin of each type (Rule 2), takes its items in position order
+ * (Rule 3, criterion drawn per position), places them (Rule 4) and divides
+ * half-full bins (Rule 5). */
+static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                      const orc_opts* o, int32_t* assign, int32_t* types,
+                      int64_t* cost, orc_stats* st) {
+  int32_t s1 = o->s1;
+  int32_t l = (m + s1 - 1) / s1;
+  uint64_t ck = orc_stream_key(o->seed, STREAM_H1);
+  int32_t* items = (int32_t*)malloc(sizeof(int32_t) * (size_t)s1);
+  int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)s1);
+  int64_t* smin = (int64_t*)malloc(sizeof(int64_t) * (size_t)s1);
+  int32_t base = 0;
+  *cost = 0;
+  for (int32_t I = 0; I < l; ++I) {
+    int32_t q0 = I * s1;
+    int32_t k = (m - q0 < s1) ? m - q0 : s1;
+    for (int32_t t = 0; t < k; ++t) items[t] = item_at(o, m, q0 + t, ORC_H1);
+    for (int32_t t = k - 1; t >= 0; --t) {
+      int64_t v = w[items[t]];
+      smin[t] = (t == k - 1 || v < smin[t + 1]) ? v : smin[t + 1];
+    }
+    opacker p;
+    pk_init(&p);
+    for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty); /* Rule 2 */
+    for (int32_t t = 0; t < k; ++t) {
+      int32_t c = o->force_crit >= 0 ? o->force_crit
+                                     : orc_criterion(ck, (uint64_t)(q0 + t));
+      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, smin[t], st);
+    }
+    base += emit_packer(&p, caps, items, local, k, base, assign, types, cost);
+    pk_free(&p);
+    if (st) st->packers += 1;
+  }
+  free(items);
+  free(local);
+  free(smin);
+  return base;
+}
+
+static int64_t factorial(int32_t k) {
+  int64_t f = 1;
+  for (int32_t i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+/* r-th permutation of 0..k-1 in lexicographic order (factorial-base digits
+ * of r select, one after another, among the values not yet used). */
+static void nth_permutation(int64_t r, int32_t k, int32_t* out) {
+  int32_t avail[8];
+  for (int32_t i = 0; i < k; ++i) avail[i] = i;
+  int32_t left = k;
+  for (int32_t t = 0; t < k; ++t) {
+    int64_t f = factorial(k - 1 - t);
+    int32_t d = (int32_t)(r / f);
+    r %= f;
+    out[t] = avail[d];
+    for (int32_t i = d; i < left - 1; ++i) avail[i] = avail[i + 1];
+    left--;
+  }
+}
+
+/* Second heuristic (Section 6.4).  Subsets of S = min(s2, m) consecutive
+ * positions; for each subset every permutation of its k items (lexicographic
+ * rank r) is packed by its own packer with Rules 2-6; the subset keeps the
+ * permutation of least cost, the lowest rank on ties; the instance cost is
+ * the sum over subsets.  Criterion of placement t of permutation r of subset
+ * I: counter (I*S! + r)*S + t of the H2 stream. */
+static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                      const orc_opts* o, int32_t* assign, int32_t* types,
+                      int64_t* cost, orc_stats* st) {
+  int32_t S = o->s2 < m ? o->s2 : m;
+  int64_t P = factorial(S);
+  int32_t l = (m + S - 1) / S;
+  uint64_t ck = orc_stream_key(o->seed, STREAM_H2);
+  int32_t items[8], order[8], placed_items[8], local[8];
+  int64_t smin[8];
+  int32_t base = 0;
+  *cost = 0;
+  for (int32_t I = 0; I < l; ++I) {
+    int32_t q0 = I * S;
+    int32_t k = (m - q0 < S) ? m - q0 : S;
+    for (int32_t t = 0; t < k; ++t) items[t] = item_at(o, m, q0 + t, ORC_H2);
+    int64_t kf = factorial(k);
+    int64_t best_cost = -1, best_r = -1;
+    for (int64_t r = 0; r < kf; ++r) {
+      nth_permutation(r, k, order);
+      for (int32_t t = k - 1; t >= 0; --t) {
+        int64_t v = w[items[order[t]]];
+        smin[t] = (t == k - 1 || v < smin[t + 1]) ? v : smin[t + 1];
+      }
+      opacker p;
+      pk_init(&p);
+      for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
+      for (int32_t t = 0; t < k; ++t) {
+        int32_t c = o->force_crit >= 0
+                        ? o->force_crit
+                        : orc_criterion(ck, (uint64_t)(((int64_t)I * P + r) * S + t));
+        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, smin[t], st);
+      }
+      int64_t c = packer_cost(&p, caps);
+      if (best_r < 0 || c < best_cost) {
+        best_cost = c;
+        best_r = r;
+      }
+      pk_free(&p);
+      if (st) st->perm_packings++;
+    }
+    /* re-run the winning permutation to emit its packing */
+    nth_permutation(best_r, k, order);
+    opacker p;
+    pk_init(&p);
+    for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
+    for (int32_t t = 0; t < k; ++t) {
+      int32_t c = o->force_crit >= 0
+                      ? o->force_crit
+                      : orc_criterion(ck, (uint64_t)(((int64_t)I * P + best_r) * S + t));
+      placed_items[t] = items[order[t]];
+      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, NULL);
+    }
+    base += emit_packer(&p, caps, placed_items, local, k, base, assign, types, cost);
+    pk_free(&p);
+    if (st) st->packers += 1;
+  }
+  return base;
+}
+
+int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                 int32_t heuristic, const orc_opts* opt, int32_t* assign,
+                 int32_t* types, int64_t* cost, orc_stats* stats) {
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL};
+  const orc_opts* o = opt ? opt : &def;
+  if (!assign || !types || !cost) return ORC_E_NULL;
+  int32_t rc = validate(w, m, caps, n, heuristic, o);
+  if (rc != ORC_OK) return rc;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  switch (heuristic) {
+    case ORC_FF:
+    case ORC_BF:
+    case ORC_WF:
+      return run_plain(w, m, caps, n, heuristic, o, assign, types, cost, stats);
+    case ORC_H1:
+      return run_h1(w, m, caps, n, o, assign, types, cost, stats);
+    default:
+      return run_h2(w, m, caps, n, o, assign, types, cost, stats);
+  }
+}
+
+int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
+                        int32_t n, const int32_t* crit, int32_t rule2,
+                        int32_t rule5, int32_t type_rule, int32_t* assign,
+                        int32_t* types, int64_t* cost) {
+  if (!w || !caps || !crit || !assign || !types || !cost) return ORC_E_NULL;
+  int32_t rc = validate(w, m, caps, n, ORC_FF, NULL);
+  if (rc != ORC_OK) return rc;
+  for (int32_t t = 0; t < m; ++t)
+    if (crit[t] < ORC_FF || crit[t] > ORC_WF) return ORC_E_OPTION;
+  int32_t* items = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  opacker p;
+  pk_init(&p);
+  if (rule2)
+    for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
+  for (int32_t t = 0; t < m; ++t) {
+    items[t] = t;
+    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, NULL);
+  }
+  *cost = 0;
+  int32_t nb = emit_packer(&p, caps, items, local, m, 0, assign, types, cost);
+  pk_free(&p);
+  free(items);
+  free(local);
+  return nb;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Lower bounds.                                                           */
+/* ---------------------------------------------------------------------- */
+
+int64_t orc_lb_sum(const int32_t* w, int32_t m) {
+  int64_t s = 0;
+  for (int32_t j = 0; j < m; ++j) s += w[j];
+  return s;
+}
+
+/* The used bins' capacities must add up to at least the total weight, and
+ * any such total is a non-negative integer combination of B_1..B_n: the least
+ * reachable total >= sum(w) (unbounded reachability table). */
+int64_t orc_lb_cap(const int32_t* w, int32_t m, const int32_t* caps, int32_t n) {
+  int64_t total = orc_lb_sum(w, m);
+  int64_t top = total + caps[0];
+  char* reach = (char*)calloc((size_t)top + 1, 1);
+  reach[0] = 1;
+  for (int64_t v = 1; v <= top; ++v)
+    for (int32_t k = 0; k < n; ++k)
+      if (v >= caps[k] && reach[v - caps[k]]) { reach[v] = 1; break; }
+  int64_t lb = top;
+  for (int64_t v = total; v <= top; ++v)
+    if (reach[v]) { lb = v; break; }
+  free(reach);
+  return lb;
+}
+
+/* Two items heavier than B_1/2 never share a bin, so each needs a bin of its
+ * own whose capacity is at least its weight. */
+int64_t orc_lb_big(const int32_t* w, int32_t m, const int32_t* caps, int32_t n) {
+  int64_t lb = 0;
+  for (int32_t j = 0; j < m; ++j) {
+    if (2 * (int64_t)w[j] > caps[0]) {
+      int32_t k = n - 1;
+      while (caps[k] < w[j]) --k;
+      lb += caps[k];
+    }
+  }
+  return lb;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Exact optimum for tiny instances.                                       */
+/* ---------------------------------------------------------------------- */
+
+/* cheapest single bin holding total s, or -1 */
+static int64_t cheapest_bin(int64_t s, const int32_t* caps, int32_t n) {
+  if (s > caps[0]) return -1;
+  for (int32_t k = n - 1; k >= 0; --k)
+    if (caps[k] >= s) return caps[k];
+  return -1;
+}
+
+/* Method 1: enumerate every set partition of the items (restricted growth
+ * strings); a block costs the smallest capacity that holds its total. */
+typedef struct {
+  const int32_t* w;
+  int32_t m;
+  const int32_t* caps;
+  int32_t n;
+  int64_t sums[16];
+  int64_t best;
+} part_ctx;
+
+static void part_rec(part_ctx* c, int32_t j, int32_t nblocks) {
+  if (j == c->m) {
+    int64_t tot = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+      int64_t cb = cheapest_bin(c->sums[b], c->caps, c->n);
+      if (cb < 0) return;
+      tot += cb;
+    }
+    if (c->best < 0 || tot < c->best) c->best = tot;
+    return;
+  }
+  for (int32_t b = 0; b <= nblocks; ++b) {
+    c->sums[b] += c->w[j];
+    if (c->sums[b] <= c->caps[0]) part_rec(c, j + 1, b == nblocks ? nblocks + 1 : nblocks);
+    c->sums[b] -= c->w[j];
+  }
+}
+
+int64_t orc_opt_partitions(const int32_t* w, int32_t m, const int32_t* caps, int32_t n) {
+  if (m < 1 || m > 12) return -1;
+  part_ctx c;
+  c.w = w; c.m = m; c.caps = caps; c.n = n; c.best = -1;
+  memset(c.sums, 0, sizeof(c.sums));
+  part_rec(&c, 0, 0);
+  return c.best;
+}
+
+/* Method 2: dynamic programme over subsets; best[S] = min over blocks T of S
+ * that contain the lowest item of S of cost(T) + best[S \ T]. */
+int64_t orc_opt_subset_dp(const int32_t* w, int32_t m, const int32_t* caps, int32_t n) {
+  if (m < 1 || m > 12) return -1;
+  uint32_t full = (1u << m) - 1u;
+  int64_t* blk = (int64_t*)malloc(sizeof(int64_t) * ((size_t)full + 1));
+  int64_t* best = (int64_t*)malloc(sizeof(int64_t) * ((size_t)full + 1));
+  for (uint32_t s = 0; s <= full; ++s) {
+    int64_t tot = 0;
+    for (int32_t j = 0; j < m; ++j)
+      if (s & (1u << j)) tot += w[j];
+    blk[s] = cheapest_bin(tot, caps, n);
+  }
+  best[0] = 0;
+  for (uint32_t s = 1; s <= full; ++s) {
+    uint32_t low = s & (~s + 1u);
+    uint32_t rest = s ^ low;
+    int64_t bs = -1;
+    /* every subset t of rest; the block is t | low */
+    uint32_t t = rest;
+    for (;;) {
+      uint32_t blkset = t | low;
+      if (blk[blkset] >= 0 && best[s ^ blkset] >= 0) {
+        int64_t v = blk[blkset] + best[s ^ blkset];
+        if (bs < 0 || v < bs) bs = v;
+      }
+      if (t == 0) break;
+      t = (t - 1) & rest;
+    }
+    best[s] = bs;
+  }
+  int64_t r = best[full];
+  free(blk);
+  free(best);
+  return r;
+}

@@ -1,0 +1,90 @@
+/*
+ * Sequential CPU oracle for the VSBPP placement heuristics of
+ * "Heuristics for the Variable Sized Bin Packing Problem Using a Hybrid
+ * P System and CUDA Architecture" (Alenezi, Aboelfotoh, Albdaiwi, Almulla).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP path; it
+ * shares no source, header or table with it.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.
+ *
+ * Problem (Section 1, "Formal Definition of VSBPP"; Section 6.1): n bin types
+ * with capacities B_1 > ... > B_n > 0 in unlimited supply, indivisible items
+ * w_1..w_m with max w <= B_1; minimise the total capacity of the used bins.
+ * All packing arithmetic is integer.
+ *
+ * Type indices are 0-based: type 0 is B_1 (the largest capacity).
+ */
+#ifndef VSBPP_ORACLE_H
+#define VSBPP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* heuristics: plain First/Best/Worst Fit (Section 1) and the two hybrid
+ * P-system heuristics (Sections 6.3 and 6.4) */
+enum { ORC_FF = 0, ORC_BF = 1, ORC_WF = 2, ORC_H1 = 3, ORC_H2 = 4 };
+/* rule for the type of a newly opened bin when no open bin fits */
+enum { ORC_TYPE_SMALLEST_FIT = 0, ORC_TYPE_LARGEST = 1 };
+enum { ORC_OK = 0, ORC_E_NULL = -1, ORC_E_SIZE = -2, ORC_E_CAPS = -3,
+       ORC_E_WEIGHT = -4, ORC_E_HEURISTIC = -5, ORC_E_OPTION = -6 };
+
+typedef struct {
+  uint64_t seed;          /* key of the counter-based generator            */
+  int32_t s1;             /* H1 items per sublist (Table 1: 10)            */
+  int32_t s2;             /* H2 subset size (Tables 1, 4, 6: 5)            */
+  int32_t type_rule;      /* ORC_TYPE_*                                    */
+  int32_t force_crit;     /* -1: drawn per placement; else ORC_FF/BF/WF    */
+  const int32_t* order;   /* optional: order[q] = item at position q       */
+} orc_opts;
+
+typedef struct {
+  int64_t packers;        /* H1 sublists / H2 subsets / 1 for plain        */
+  int64_t perm_packings;  /* H2: permutations packed (sum of k!)           */
+  int64_t placements;     /* item placements performed                     */
+  int64_t bin_tests;      /* open bins visited by fit tests                */
+  int64_t live_tests;     /* open bins that could still take any item      */
+  int64_t new_bins;       /* bins opened because nothing fitted            */
+  int64_t divisions;      /* Rule-5 divisions                              */
+} orc_stats;
+
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the k-th output (k >= 0)
+ * of the generator whose state starts at `seed`. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k);
+/* derived per-purpose key: output `stream` of the generator at `seed` */
+uint64_t orc_stream_key(uint64_t seed, uint64_t stream);
+/* criterion draw in {0,1,2} = {FF,BF,WF} with equal probabilities */
+int32_t orc_criterion(uint64_t stream_key, uint64_t counter);
+/* pseudo-random permutation of [0,m): the item at position q (Rule 1) */
+int32_t orc_perm(uint64_t seed, int32_t m, int32_t q);
+
+/* Runs one heuristic on one instance.  assign[m] receives a bin id per item,
+ * types[m] the type index of bins 0..nbins-1.  Returns nbins (>= 1) or a
+ * negative ORC_E_* code; nothing is written on error.  stats may be NULL. */
+int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                 int32_t heuristic, const orc_opts* opt, int32_t* assign,
+                 int32_t* types, int64_t* cost, orc_stats* stats);
+
+/* One packer of the hybrid P system with explicit per-placement criteria:
+ * Rule-2 bins (one empty bin per type) when rule2 != 0, Rule-5 division when
+ * rule5 != 0.  Items are placed in the given order.  Same outputs as
+ * orc_pack (used bins only, creation order). */
+int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
+                        int32_t n, const int32_t* crit, int32_t rule2,
+                        int32_t rule5, int32_t type_rule, int32_t* assign,
+                        int32_t* types, int64_t* cost);
+
+/* lower bounds on the optimum */
+int64_t orc_lb_sum(const int32_t* w, int32_t m);
+int64_t orc_lb_cap(const int32_t* w, int32_t m, const int32_t* caps, int32_t n);
+int64_t orc_lb_big(const int32_t* w, int32_t m, const int32_t* caps, int32_t n);
+
+/* exact optimum, two independent methods (m <= 12) */
+int64_t orc_opt_partitions(const int32_t* w, int32_t m, const int32_t* caps, int32_t n);
+int64_t orc_opt_subset_dp(const int32_t* w, int32_t m, const int32_t* caps, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
