@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""Benchmark of the VSBPP placement hot path on one MI355X.
+
+Workload: the uniform batch -- 4096 instances x 1000 items, 5 bin types with
+B_1 = 200 and four distinct capacities from [100,199], weights uniform in
+[1,200] (synthetic, seeded).  One step packs the whole batch, resident in
+HBM, with every heuristic of the path: plain First/Best/Worst Fit and the two
+hybrid-P-system heuristics (one launch each).  The value is items placed per
+second over the whole step (each heuristic places every item of the batch).
+
+Prints one JSON line.  Per-kernel durations come from HIP events recorded
+around every launch on the launch stream during the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HEURISTICS = ("FF", "BF", "WF", "H1", "H2")
+
+# Algorithmic work per item on the uniform-batch distribution, from the
+# oracle's instrumented run (bin tests: open bins visited by the fit test;
+# for FF/BF/WF the live ones, i.e. room >= smallest weight still to come; for
+# the P-system packers every bin of the packer).  Re-measured by the
+# CPU-baseline leg on its own sample and reported next to these.
+BIN_TESTS_PER_ITEM = {"FF": 235.1, "BF": 232.8, "WF": 339.5, "H1": 6.2, "H2": 574.0}
+OPS_PER_BIN_TEST = 2          # form the room-after key, fold it into the min
+ALU_PEAK = 256 * 4 * 16 * 2.4e9   # int32 VALU lane-ops/s: CUs x SIMDs x lanes x clock
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--instances", type=int, default=4096)
+    ap.add_argument("--items", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--heuristics", default=",".join(HEURISTICS))
+    return ap.parse_args()
+
+
+def cpu_baseline(batch, heuristics, n_sample):
+    """The oracle (sequential C, one instance per call) on a bounded sample of
+    the same batch, on the host cores via a thread pool."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle.build()
+    idx = list(range(min(n_sample, batch.n_instances)))
+    cores = max(1, min(16, os.cpu_count() or 1))
+    counts = {h: [0, 0] for h in heuristics}
+
+    def one(args):
+        h, i = args
+        w, caps, _ = batch.instance(i)
+        r = oracle.pack(w, caps, h, seed=int(batch.seeds[i]))
+        return h, r.stats["live_tests"] if h in ("FF", "BF", "WF") else r.stats["bin_tests"], w.size
+
+    jobs = [(h, i) for h in heuristics for i in idx]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        for h, tests, m in ex.map(one, jobs):
+            counts[h][0] += tests
+            counts[h][1] += m
+    dt = time.perf_counter() - t0
+    items = sum(c[1] for c in counts.values())
+    per_item = {h: round(c[0] / max(c[1], 1), 1) for h, c in counts.items()}
+    return {
+        "value": items / dt,
+        "unit": "items/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(idx)} of {batch.n_instances} instances x {len(heuristics)} heuristics "
+                  f"({items} item placements), {dt:.2f} s wall on {cores} threads",
+    }, per_item
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the packing path is measured on a single "
+              "MI355X (instances shard across GPUs with no exchange; no multi-GPU run is "
+              "part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1602_08735_amd as V
+    from paper_1602_08735_amd import inputs
+
+    heuristics = tuple(h for h in args.heuristics.split(",") if h)
+    batch = inputs.config2(n_instances=args.instances, m=args.items)
+    db = V.DeviceBatch(batch)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        for k, h in enumerate(heuristics):
+            if ev is not None:
+                ev[k][0].record(stream)
+            V.pack_batch(db, h, stream=stream)
+            if ev is not None:
+                ev[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in heuristics] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for s in range(args.steps):
+        step(evs[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_step = total_ms / args.steps
+    kern_ms = {h: float(np.mean([evs[s][k][0].elapsed_time(evs[s][k][1])
+                                  for s in range(args.steps)]))
+               for k, h in enumerate(heuristics)}
+    items = batch.total_items
+    value = len(heuristics) * items / (ms_step / 1e3)
+
+    # outputs of every heuristic once more, for the quality figures
+    quality = {}
+    for h in heuristics:
+        V.pack_batch(db, h, stream=stream)
+        torch.cuda.synchronize()
+        nb = db.nbins.cpu().numpy()
+        if (nb < 0).any():
+            raise RuntimeError(f"{h}: device reported instance errors")
+        cost = db.cost.cpu().numpy().astype(np.float64)
+        quality[h] = {"mean_cost": float(cost.mean()),
+                      "mean_utilisation": float((np.add.reduceat(
+                          batch.weights.astype(np.int64), batch.item_off[:-1]) / cost).mean())}
+
+    per_kernel = {}
+    for h in heuristics:
+        ops = OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[h] * items
+        achieved = ops / (kern_ms[h] / 1e3)
+        per_kernel[h] = {"ms": round(kern_ms[h], 4),
+                         "items_per_s": items / (kern_ms[h] / 1e3),
+                         "alu_frac": achieved / ALU_PEAK}
+    dom = max(heuristics, key=lambda h: kern_ms[h])
+    ops_dom = OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[dom] * items
+    achieved = ops_dom / (kern_ms[dom] / 1e3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "kernel": f"pack {dom}",
+        "achieved": achieved,
+        "peak": ALU_PEAK / 1e12,
+        "unit": "Tops/s",
+        "frac": achieved / (ALU_PEAK / 1e12),
+        "traffic": None,
+        "work_per_launch": f"{OPS_PER_BIN_TEST} ops x {BIN_TESTS_PER_ITEM[dom]} bin tests/item "
+                           f"x {items} items",
+    }
+    out = {
+        "metric": "items placed/sec, batched VSBPP heuristics; mean cost/LB, learned vs plain",
+        "value": value,
+        "unit": "items/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"uniform batch: {args.instances} instances x {args.items} items, "
+                        "5 bin types (B_1=200, 4 distinct in [100,199]), w~U[1,200]; "
+                        f"heuristics {','.join(heuristics)} one launch each",
+            "instances": args.instances,
+            "items_per_instance": args.items,
+            "heuristics": list(heuristics),
+        },
+        "roofline": roofline,
+        "per_kernel": per_kernel,
+        "instances_per_s": len(heuristics) * args.instances / (ms_step / 1e3),
+        "h2_permutation_placements_per_s": (120 * items / (kern_ms["H2"] / 1e3)
+                                            if "H2" in kern_ms else None),
+        "quality": quality,
+    }
+    if not args.no_cpu_baseline:
+        cb, per_item = cpu_baseline(batch, heuristics, args.cpu_sample)
+        out["cpu_baseline"] = cb
+        out["cpu_measured_bin_tests_per_item"] = per_item
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

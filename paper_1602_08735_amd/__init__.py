@@ -1,0 +1,198 @@
+"""MI355X (gfx950) implementation of the placement hot path of the VSBPP
+heuristics of Alenezi, Aboelfotoh, Albdaiwi & Almulla (hybrid P system).
+
+Thin Python binding over the C ABI in ``include/vsbpp.h`` (``libvsbpp.so``):
+argument marshalling only, every packing step runs in the HIP kernels.
+PyTorch provides device memory and streams for the batched entry point.
+The library is loaded on first use; a missing library raises instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvsbpp.so")
+
+FF, BF, WF, H1, H2 = 0, 1, 2, 3, 4
+HEURISTICS = {"FF": FF, "BF": BF, "WF": WF, "H1": H1, "H2": H2}
+TYPE_SMALLEST_FIT, TYPE_LARGEST = 0, 1
+
+ERRORS = {
+    -1: "E_NULL", -2: "E_SIZE", -3: "E_CAPS", -4: "E_WEIGHT", -5: "E_HEURISTIC",
+    -6: "E_OPTION", -7: "E_DEVICE", -8: "E_NOMEM",
+}
+
+# exported symbols, as declared in include/vsbpp.h
+EXPORTS = (
+    "vsbpp_options_init", "vsbpp_pack", "vsbpp_pack_ex", "vsbpp_pack_batch",
+    "vsbpp_best_of", "vsbpp_strerror", "vsbpp_device_ok",
+)
+
+
+class VsbppError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = int(code)
+        super().__init__(f"{what}: {ERRORS.get(self.code, self.code)} ({self.code})")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("h1_items_per_sublist", ctypes.c_int32),
+        ("h2_subset_size", ctypes.c_int32),
+        ("type_rule", ctypes.c_int32),
+        ("force_criterion", ctypes.c_int32),
+        ("order", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libvsbpp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_1602_08735_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        vp = ctypes.c_void_p
+        L.vsbpp_options_init.restype = None
+        L.vsbpp_options_init.argtypes = [ctypes.POINTER(Options)]
+        L.vsbpp_pack.restype = i32
+        L.vsbpp_pack.argtypes = [vp, i32, vp, i32, i32, vp, vp]
+        L.vsbpp_pack_ex.restype = i32
+        L.vsbpp_pack_ex.argtypes = [vp, i32, vp, i32, i32, ctypes.POINTER(Options), vp, vp,
+                                    ctypes.POINTER(i64)]
+        L.vsbpp_pack_batch.restype = i32
+        L.vsbpp_pack_batch.argtypes = [i32, vp, vp, vp, vp, i32, i32, i32, i32,
+                                       ctypes.POINTER(Options), vp, vp, vp, vp, vp, vp, vp]
+        L.vsbpp_best_of.restype = i32
+        L.vsbpp_best_of.argtypes = [vp, i32, vp, vp]
+        L.vsbpp_strerror.restype = ctypes.c_char_p
+        L.vsbpp_strerror.argtypes = [i32]
+        L.vsbpp_device_ok.restype = i32
+        L.vsbpp_device_ok.argtypes = []
+        _lib = L
+    return _lib
+
+
+def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT,
+            force_crit: int = -1) -> Options:
+    o = Options()
+    lib().vsbpp_options_init(ctypes.byref(o))
+    o.seed = seed & (2**64 - 1)
+    o.h1_items_per_sublist = s1
+    o.h2_subset_size = s2
+    o.type_rule = type_rule
+    o.force_criterion = force_crit
+    return o
+
+
+def strerror(code: int) -> str:
+    return lib().vsbpp_strerror(code).decode()
+
+
+def device_ok() -> bool:
+    return bool(lib().vsbpp_device_ok())
+
+
+@dataclass
+class Packing:
+    assignment: np.ndarray
+    bin_types: np.ndarray
+    nbins: int
+    cost: int
+
+
+def _heur(h) -> int:
+    return HEURISTICS[h] if isinstance(h, str) else int(h)
+
+
+def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
+         type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, order=None) -> Packing:
+    """One instance through vsbpp_pack_ex (host arrays, synchronous)."""
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(caps, dtype=np.int32))
+    m = int(w.size)
+    a = np.zeros(max(m, 1), dtype=np.int32)
+    t = np.zeros(max(m, 1), dtype=np.int32)
+    cost = ctypes.c_int64(0)
+    o = options(seed, s1, s2, type_rule, force_crit)
+    ordv = None
+    if order is not None:
+        ordv = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+        o.order = ordv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    rc = lib().vsbpp_pack_ex(w.ctypes.data, m, c.ctypes.data, int(c.size), _heur(heuristic),
+                             ctypes.byref(o), a.ctypes.data, t.ctypes.data, ctypes.byref(cost))
+    if rc < 0:
+        raise VsbppError(rc, "vsbpp_pack_ex")
+    return Packing(a[:m].copy(), t[:rc].copy(), int(rc), int(cost.value))
+
+
+class DeviceBatch:
+    """A batch of instances resident in device memory (torch tensors).
+
+    ``weights``/``order`` int32 [sum m], ``item_off`` int64 [N+1], ``caps``
+    int32 [sum n], ``cap_off`` int32 [N+1], ``seeds`` uint64 as int64 [N]."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+
+        self.n = batch.n_instances
+        self.total = batch.total_items
+        self.max_items = max(1, batch.max_m)
+        ncap = np.diff(batch.cap_off)
+        self.max_types = int(ncap.max()) if ncap.size else 1
+        self.max_cap = int(max(
+            (batch.caps[batch.cap_off[i]] for i in range(self.n) if ncap[i] > 0), default=1))
+        t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dt)
+        self.weights = t(batch.weights, torch.int32)
+        self.item_off = t(batch.item_off, torch.int64)
+        self.caps = t(batch.caps, torch.int32)
+        self.cap_off = t(batch.cap_off, torch.int32)
+        self.order = None if batch.order is None else t(batch.order, torch.int32)
+        self.seeds = None if batch.seeds is None else t(
+            batch.seeds.astype(np.uint64).view(np.int64), torch.int64)
+        self.assignment = torch.empty(max(self.total, 1), dtype=torch.int32, device=device)
+        self.bin_types = torch.empty(max(self.total, 1), dtype=torch.int32, device=device)
+        self.nbins = torch.empty(max(self.n, 1), dtype=torch.int32, device=device)
+        self.cost = torch.empty(max(self.n, 1), dtype=torch.int64, device=device)
+
+
+def pack_batch(db: DeviceBatch, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
+               type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, stream=None,
+               use_order: bool = True, use_seeds: bool = True) -> None:
+    """Launches vsbpp_pack_batch on the given torch stream (default: current).
+    Results land in db.assignment / db.bin_types / db.nbins / db.cost."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    o = options(seed, s1, s2, type_rule, force_crit)
+    ptr = lambda x: None if x is None else x.data_ptr()
+    rc = lib().vsbpp_pack_batch(
+        db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
+        db.max_items, db.max_types, db.max_cap, _heur(heuristic), ctypes.byref(o),
+        ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
+        ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost),
+        ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_pack_batch")
+
+
+def best_of(cost_tensor, num: int, out_tensor, stream=None) -> None:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().vsbpp_best_of(cost_tensor.data_ptr(), num, out_tensor.data_ptr(),
+                             ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_best_of")

@@ -1,0 +1,160 @@
+// Wavefront primitives and the counter-based generator used by every
+// packing kernel (gfx950, 64-lane wavefronts).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vsbpp {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() {
+  return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ int32_t readlane(int32_t v, int l) {
+  return __builtin_amdgcn_readlane(v, l);
+}
+__device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
+  uint32_t lo = readlane((uint32_t)v, l), hi = readlane((uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// DPP move with an explicit fill value for lanes the control does not write.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t fill, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// DPP controls (GFX9 encoding)
+constexpr int kQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+constexpr int kRowBcast15 = 0x142;
+constexpr int kRowBcast31 = 0x143;
+constexpr int kRowShr1 = 0x111;
+
+// Unsigned minimum over the 64 lanes; the result is wave-uniform.  All lanes
+// must be active.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+  constexpr uint32_t I = 0xFFFFFFFFu;
+  v = min(v, dpp<kQuadSwap1>(I, v));
+  v = min(v, dpp<kQuadSwap2>(I, v));
+  v = min(v, dpp<kRowHalfMirror>(I, v));
+  v = min(v, dpp<kRowMirror>(I, v));
+  v = min(v, dpp<kRowBcast15, 0xA>(I, v));
+  v = min(v, dpp<kRowBcast31, 0xC>(I, v));
+  return readlane(v, 63);
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint64_t dpp64(uint64_t fill, uint64_t v) {
+  uint32_t lo = dpp<CTRL, ROWS>((uint32_t)fill, (uint32_t)v);
+  uint32_t hi = dpp<CTRL, ROWS>((uint32_t)(fill >> 32), (uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_min(uint64_t v) {
+  constexpr uint64_t I = ~0ull;
+  v = min(v, dpp64<kQuadSwap1>(I, v));
+  v = min(v, dpp64<kQuadSwap2>(I, v));
+  v = min(v, dpp64<kRowHalfMirror>(I, v));
+  v = min(v, dpp64<kRowMirror>(I, v));
+  v = min(v, dpp64<kRowBcast15, 0xA>(I, v));
+  v = min(v, dpp64<kRowBcast31, 0xC>(I, v));
+  return readlane(v, 63);
+}
+
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+  return (int32_t)(wave_min((uint32_t)v ^ 0x80000000u) ^ 0x80000000u);
+}
+
+// Inclusive prefix sum over the 64 lanes (all lanes active).
+__device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).  Output k of the generator
+// whose state starts at `seed`: the state seed + (k+1)*gamma through the
+// published 64-bit finaliser.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t s = seed + (k + 1ull) * 0x9e3779b97f4a7c15ull;
+  s ^= s >> 30;
+  s *= 0xbf58476d1ce4e5b9ull;
+  s ^= s >> 27;
+  s *= 0x94d049bb133111ebull;
+  return s ^ (s >> 31);
+}
+
+// generator streams (one key per purpose, derived from the instance seed)
+constexpr uint64_t kStreamRule1 = 1, kStreamH1 = 2, kStreamH2 = 3;
+
+__device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t stream) {
+  return splitmix64(seed, stream);
+}
+
+// Rule 3 criterion: FF/BF/WF with equal probability, floor(3*hi32 / 2^32).
+__device__ __forceinline__ int draw_criterion(uint64_t key, uint64_t counter) {
+  uint64_t hi = splitmix64(key, counter) >> 32;
+  return (int)((hi * 3ull) >> 32);
+}
+
+// Rule 1 distribution: keyed permutation of [0,m) from a 4-round balanced
+// Feistel network on 2h bits (2^(2h) >= m, round function = generator output
+// for counter (round << 32 | right half)), restricted to [0,m) by cycle
+// walking (Black & Rogaway, CT-RSA 2002).
+struct Rule1Perm {
+  uint64_t key;
+  uint32_t h, mask, m;
+  __device__ void init(uint64_t seed, uint32_t m_) {
+    m = m_;
+    uint32_t bits = 0;
+    while ((1u << bits) < m && bits < 31) ++bits;
+    h = (bits + 1) >> 1;
+    mask = (1u << h) - 1u;
+    key = stream_key(seed, kStreamRule1);
+  }
+  __device__ __forceinline__ uint32_t round_trip(uint32_t x) const {
+    uint32_t l = x >> h, r = x & mask;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+      uint32_t f = (uint32_t)splitmix64(key, ((uint64_t)i << 32) | r) & mask;
+      uint32_t t = l ^ f;
+      l = r;
+      r = t;
+    }
+    return (l << h) | r;
+  }
+  __device__ uint32_t at(uint32_t q) const {
+    if (m <= 1) return 0;
+    uint32_t y = round_trip(q);
+    while (y >= m) y = round_trip(y);
+    return y;
+  }
+};
+
+}  // namespace vsbpp

@@ -1,0 +1,596 @@
+// The two hybrid-P-system heuristics (paper Sections 6.3 and 6.4).
+//
+// One workgroup per instance; every thread is one packer of the P system:
+//   H1: thread <-> sublist S_I (s1 consecutive positions of the Rule-1 order);
+//   H2: thread <-> (subset I, permutation rank r); a group of
+//       roundup(S!, 64) threads covers the S! permutations of one subset and a
+//       group minimum of (cost, r) picks the subset's packing.
+// A packer starts with one empty bin of each type (Rule 2), takes its items in
+// order (Rule 3, criterion drawn per placement), places each by FF/BF/WF among
+// the bins it fits (Rule 4, lowest index on ties), opens a bin of the chosen
+// type when none fits, and divides a bin once when its load reaches half its
+// capacity (Rule 5).
+//
+// Packer bins live in LDS, per thread: words of bin b of thread t sit at
+// (b >> 2) * 4*blockDim + 4*t + (b & 3), so one 16-byte load per lane reads
+// four bins and lanes are unit-stride.  Output bin ids are canonical: used
+// bins (load > 0) in creation order, packers in sublist/subset order; the
+// per-instance id offsets come from a block scan over the packers.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace vsbpp {
+namespace {
+
+constexpr int FF = 0, BF = 1, WF = 2;
+
+template <typename K>
+struct PK;
+template <>
+struct PK<uint32_t> {
+  static constexpr int SH = 16;
+  static constexpr int32_t R = 0x7FFF;
+  static constexpr uint32_t TOP = 0x80000000u;
+};
+template <>
+struct PK<uint64_t> {
+  static constexpr int SH = 32;
+  static constexpr int32_t R = 0x7FFFFFFF;
+  static constexpr uint64_t TOP = 0x8000000000000000ull;
+};
+
+// Per-thread packer over LDS-resident bins.  With 32-bit keys (B_1 <= 32767)
+// a bin is one word (capacity << 16 | room); with 64-bit keys room and
+// capacity are two words in two arrays.  An empty slot (no bin) has room 0
+// and capacity 0 (packed) or room -1 (split), so no item fits it.
+template <typename K>
+struct LanePacker {
+  static constexpr bool kPacked = sizeof(K) == 4;
+  int32_t* room;  // this thread's words (bin b at (b>>2)*stride + (b&3))
+  int32_t* cap;   // split layout only
+  int stride;     // 4 * blockDim
+  uint64_t div;   // Rule-5 "already divided" marks
+  int nb;
+
+  __device__ __forceinline__ int widx(int b) const { return (b >> 2) * stride + (b & 3); }
+  __device__ __forceinline__ int32_t room_at(int b) const {
+    return kPacked ? (room[widx(b)] & 0xFFFF) : room[widx(b)];
+  }
+  __device__ __forceinline__ int32_t cap_at(int b) const {
+    return kPacked ? (int32_t)((uint32_t)room[widx(b)] >> 16) : cap[widx(b)];
+  }
+  __device__ __forceinline__ void set_bin(int b, int32_t c, int32_t r) {
+    if constexpr (kPacked) {
+      room[widx(b)] = (int32_t)(((uint32_t)c << 16) | (uint32_t)r);
+    } else {
+      room[widx(b)] = r;
+      cap[widx(b)] = c;
+    }
+  }
+
+  // Rule 2: one empty bin per type; slots [n, nbslots) hold no bin.
+  __device__ void init(const int32_t* scaps, int n, int nbslots) {
+    for (int g = 0; g < (nbslots >> 2); ++g) {
+      int4 r, c;
+      int* rp = &r.x;
+      int* cp = &c.x;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = (g << 2) + j;
+        const int32_t v = b < n ? scaps[b] : 0;
+        if constexpr (kPacked) {
+          rp[j] = (int32_t)(((uint32_t)v << 16) | (uint32_t)v);
+        } else {
+          cp[j] = v;
+          rp[j] = b < n ? v : -1;
+        }
+      }
+      *reinterpret_cast<int4*>(room + g * stride) = r;
+      if constexpr (!kPacked) *reinterpret_cast<int4*>(cap + g * stride) = c;
+    }
+    div = 0;
+    nb = n;
+  }
+
+  // Places weight w with criterion crit; nbound is a wave-uniform upper bound
+  // on nb.  Returns the bin index used.
+  __device__ int place(int32_t w, int crit, int nbound, const int32_t* scaps, int n,
+                       int type_rule) {
+    using T = PK<K>;
+    const int32_t mul = crit == BF ? 1 : (crit == WF ? -1 : 0);
+    const int32_t add = crit == WF ? T::R : 0;
+    K best = ~(K)0;
+    const int ng = (nbound + 3) >> 2;
+    for (int g = 0; g < ng; ++g) {
+      const int4 r4 = *reinterpret_cast<const int4*>(room + g * stride);
+      const int* rp = &r4.x;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t rm = kPacked ? (rp[j] & 0xFFFF) : rp[j];
+        const int32_t after = rm - w;
+        const int32_t sel = mul * after + add;
+        K key = ((K)(uint32_t)sel << T::SH) | (K)((g << 2) + j);
+        if (after < 0) key |= T::TOP;
+        best = min(best, key);
+      }
+    }
+    int b;
+    int32_t bcap, broom;
+    if (best < T::TOP) {
+      b = (int)(best & (K)0xFF);
+      broom = room_at(b);
+      bcap = cap_at(b);
+    } else {
+      // nothing fits: open a bin (smallest capacity >= w, or B_1)
+      int t = 0;
+      if (type_rule != 1)
+        for (int k = 1; k < n; ++k) t += scaps[k] >= w ? 1 : 0;
+      bcap = scaps[t];
+      broom = bcap;
+      b = nb++;
+    }
+    broom -= w;
+    set_bin(b, bcap, broom);
+    // Rule 5: a bin at least half full divides once
+    if (!((div >> b) & 1ull) && 2ll * (bcap - broom) >= (long long)bcap) {
+      div |= 1ull << b;
+      set_bin(nb, bcap, bcap);
+      ++nb;
+    }
+    return b;
+  }
+
+  // bins with load > 0, as a bit mask over bin indices, and their cost
+  __device__ uint64_t used(int64_t* cost) const {
+    uint64_t u = 0;
+    int64_t c = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int32_t cb = cap_at(b);
+      if (room_at(b) < cb) {
+        u |= 1ull << b;
+        c += cb;
+      }
+    }
+    *cost = c;
+    return u;
+  }
+
+  __device__ int type_of(int b, const int32_t* scaps, int n) const {
+    const int32_t cb = cap_at(b);
+    int t = 0;
+    for (int k = 0; k < n; ++k)
+      if (scaps[k] == cb) t = k;
+    return t;
+  }
+};
+
+// block-wide exclusive scan of v; returns the prefix and writes the total
+__device__ int32_t block_excl_scan(int32_t v, int32_t* s_tmp, int32_t* total) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int32_t incl = wave_incl_sum(v);
+  if (lane == kWave - 1) s_tmp[wave] = incl;
+  __syncthreads();
+  int32_t before = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int32_t x = s_tmp[i];
+    before += i < wave ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + incl - v;
+}
+
+__device__ int64_t block_sum64(int64_t v, int64_t* s_tmp) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+  if (lane == 0) s_tmp[wave] = v;
+  __syncthreads();
+  int64_t t = 0;
+  for (int i = 0; i < nw; ++i) t += s_tmp[i];
+  __syncthreads();
+  return t;
+}
+
+// Block-level validation of instance `inst`.  Returns 0 or an error code
+// (uniform across the block) and loads the capacities into s_caps.
+__device__ int validate_block(const BatchArgs& a, int inst, int64_t off, int m, int c0, int n,
+                              int32_t* s_caps, int* s_flag) {
+  if ((int64_t)m < 1 || m > a.max_items || n < 1 || n > kMaxTypes || n > a.max_types)
+    return kErrSize;
+  const int tid = threadIdx.x;
+  if (tid < kMaxTypes) s_caps[tid] = tid < n ? a.caps[c0 + tid] : 0;
+  __syncthreads();
+  int bad = 0;
+  if (tid < n) {
+    const int32_t c = s_caps[tid];
+    if (c <= 0 || (tid > 0 && c >= s_caps[tid - 1])) bad = 1;
+  }
+  if (__syncthreads_or(bad)) return kErrCaps;
+  const int32_t B1 = s_caps[0];
+  if (B1 > a.max_cap) return kErrSize;
+  int badw = 0, bado = 0;
+  for (int q = tid; q < m; q += blockDim.x) {
+    const int32_t w = a.w[off + q];
+    badw |= (w < 1 || w > B1);
+    if (a.order) {
+      const int32_t it = a.order[off + q];
+      bado |= ((unsigned)it >= (unsigned)m);
+    }
+  }
+  if (__syncthreads_or(badw)) return kErrWeight;
+  if (__syncthreads_or(bado)) return kErrOption;
+  (void)inst;
+  (void)s_flag;
+  return 0;
+}
+
+__device__ __forceinline__ uint64_t inst_seed(const BatchArgs& a, int inst) {
+  return a.seeds ? a.seeds[inst] : a.seed;
+}
+
+// ---------------------------------------------------------------------------
+// First heuristic (Section 6.3)
+// ---------------------------------------------------------------------------
+template <typename K>
+__global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t s_caps[kMaxTypes];
+  __shared__ int32_t s_scan[16];
+  __shared__ int64_t s_sum[16];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, B = blockDim.x;
+  constexpr int kArrays = sizeof(K) == 4 ? 1 : 2;
+  int32_t* lroom = reinterpret_cast<int32_t*>(smem);
+  int32_t* lcap = lroom + (size_t)nbslots * B;
+  int32_t* litem = lroom + (size_t)kArrays * nbslots * B;  // [s1][B]
+  uint8_t* lloc = reinterpret_cast<uint8_t*>(litem + (size_t)a.s1 * B);  // [s1][B]
+
+  LanePacker<K> pk;
+  pk.room = lroom + 4 * tid;
+  pk.cap = lcap + 4 * tid;
+  pk.stride = 4 * B;
+
+  for (int inst = blockIdx.x; inst < a.num; inst += gridDim.x) {
+    const int64_t off = a.item_off[inst];
+    const int64_t m64 = a.item_off[inst + 1] - off;
+    const int c0 = a.cap_off[inst];
+    const int n = a.cap_off[inst + 1] - c0;
+    const int m = m64 > 0x7FFFFFFF ? 0x7FFFFFFF : (int)m64;
+    const int err = m64 > a.max_items ? kErrSize
+                                       : validate_block(a, inst, off, m, c0, n, s_caps, &s_flag);
+    if (err) {
+      if (tid == 0) {
+        a.nbins[inst] = err;
+        a.cost[inst] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const uint64_t seed = inst_seed(a, inst);
+    Rule1Perm perm;
+    perm.init(seed, (uint32_t)m);
+    const uint64_t ck = stream_key(seed, kStreamH1);
+    const int s1 = a.s1;
+    const int l = (m + s1 - 1) / s1;
+    int32_t carry = 0;
+    int64_t cost_acc = 0;
+    for (int base_I = 0; base_I < l; base_I += B) {
+      const int I = base_I + tid;
+      const bool active = I < l;
+      const int q0 = I * s1;
+      const int k = active ? min(s1, m - q0) : 0;
+      if (active) pk.init(s_caps, n, nbslots);
+      for (int t = 0; t < s1; ++t) {
+        if (t < k) {
+          const int q = q0 + t;
+          const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
+          const int32_t w = a.w[off + item];
+          const int crit = a.force_crit >= 0 ? a.force_crit : draw_criterion(ck, (uint64_t)q);
+          const int b = pk.place(w, crit, min(nbslots, n + 2 * t), s_caps, n, a.type_rule);
+          litem[t * B + tid] = item;
+          lloc[t * B + tid] = (uint8_t)b;
+        }
+      }
+      int64_t c = 0;
+      uint64_t u = 0;
+      if (active) u = pk.used(&c);
+      int32_t total;
+      const int32_t before = block_excl_scan((int32_t)__popcll(u), s_scan, &total);
+      const int32_t gbase = carry + before;
+      if (active) {
+        for (int t = 0; t < k; ++t) {
+          const int b = lloc[t * B + tid];
+          const int rank = (int)__popcll(u & ((1ull << b) - 1ull));
+          a.assign[off + litem[t * B + tid]] = gbase + rank;
+        }
+        uint64_t uu = u;
+        int r = 0;
+        while (uu) {
+          const int b = __builtin_ctzll(uu);
+          uu &= uu - 1;
+          a.types[off + gbase + r] = pk.type_of(b, s_caps, n);
+          ++r;
+        }
+      }
+      carry += total;
+      cost_acc += block_sum64(c, s_sum);
+    }
+    if (tid == 0) {
+      a.nbins[inst] = carry;
+      a.cost[inst] = cost_acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Second heuristic (Section 6.4)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int factorial_small(int k) {
+  int f = 1;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+// r-th permutation of 0..k-1 in lexicographic order, as 4-bit digits
+// (digit t = the item placed t-th).
+__device__ __forceinline__ uint32_t nth_perm(int r, int k) {
+  uint32_t avail = 0x543210u;
+  uint32_t out = 0;
+  for (int t = 0; t < k; ++t) {
+    const int f = factorial_small(k - 1 - t);
+    const int d = r / f;
+    r -= d * f;
+    const uint32_t v = (avail >> (4 * d)) & 0xFu;
+    const uint32_t lowmask = (1u << (4 * d)) - 1u;
+    avail = (avail & lowmask) | ((avail >> (4 * d + 4)) << (4 * d));
+    out |= v << (4 * t);
+  }
+  return out;
+}
+
+constexpr int kMaxSubset = 6;
+
+template <typename K>
+__global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t s_caps[kMaxTypes];
+  __shared__ uint64_t s_wmin[16];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, B = blockDim.x;
+  const int spr = B / group;  // subsets per round
+  constexpr int kArrays = sizeof(K) == 4 ? 1 : 2;
+  int32_t* lroom = reinterpret_cast<int32_t*>(smem);
+  int32_t* lcap = lroom + (size_t)nbslots * B;
+  int32_t* s_item = lroom + (size_t)kArrays * nbslots * B;  // [spr][6]
+  int32_t* s_w = s_item + spr * kMaxSubset;                // [spr][6]
+  int32_t* s_loc = s_w + spr * kMaxSubset;                 // [spr][6] canonical local id
+  int32_t* s_typ = s_loc + spr * kMaxSubset;               // [spr][6]
+  int32_t* s_u = s_typ + spr * kMaxSubset;                 // [spr]
+  int32_t* s_base = s_u + spr;                             // [spr]
+  int64_t* s_cst = reinterpret_cast<int64_t*>(s_base + spr);  // [spr], 8-byte aligned
+
+  LanePacker<K> pk;
+  pk.room = lroom + 4 * tid;
+  pk.cap = lcap + 4 * tid;
+  pk.stride = 4 * B;
+  const int g = tid / group, r = tid - g * group;
+  const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
+
+  for (int inst = blockIdx.x; inst < a.num; inst += gridDim.x) {
+    const int64_t off = a.item_off[inst];
+    const int64_t m64 = a.item_off[inst + 1] - off;
+    const int c0 = a.cap_off[inst];
+    const int n = a.cap_off[inst + 1] - c0;
+    const int m = m64 > 0x7FFFFFFF ? 0x7FFFFFFF : (int)m64;
+    const int err = m64 > a.max_items ? kErrSize
+                                       : validate_block(a, inst, off, m, c0, n, s_caps, &s_flag);
+    if (err) {
+      if (tid == 0) {
+        a.nbins[inst] = err;
+        a.cost[inst] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const uint64_t seed = inst_seed(a, inst);
+    Rule1Perm perm;
+    perm.init(seed, (uint32_t)m);
+    const uint64_t ck = stream_key(seed, kStreamH2);
+    const int S = min(a.s2, m);
+    const int P = factorial_small(S);
+    const int l = (m + S - 1) / S;
+    int32_t carry = 0;
+    int64_t cost_acc = 0;
+    for (int base_I = 0; base_I < l; base_I += spr) {
+      const int I = base_I + g;
+      const int q0 = I * S;
+      const int k = I < l ? min(S, m - q0) : 0;
+      const int kf = factorial_small(k);
+      const bool active = k > 0 && r < kf;
+      // stage the subset's items
+      if (r < k) {
+        const int q = q0 + r;
+        const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
+        s_item[g * kMaxSubset + r] = item;
+        s_w[g * kMaxSubset + r] = a.w[off + item];
+      }
+      __syncthreads();
+      uint64_t key = ~0ull;
+      uint64_t locs = 0;
+      uint64_t u = 0;
+      int64_t c = 0;
+      if (active) {
+        pk.init(s_caps, n, nbslots);
+        const uint32_t pm = nth_perm(r, k);
+        for (int t = 0; t < k; ++t) {
+          const int d = (pm >> (4 * t)) & 0xF;
+          const int32_t w = s_w[g * kMaxSubset + d];
+          const int crit = a.force_crit >= 0
+                               ? a.force_crit
+                               : draw_criterion(ck, ((uint64_t)I * (uint64_t)P + (uint64_t)r) *
+                                                            (uint64_t)S + (uint64_t)t);
+          const int b = pk.place(w, crit, min(nbslots, n + 2 * t), s_caps, n, a.type_rule);
+          locs |= (uint64_t)b << (6 * d);
+        }
+        u = pk.used(&c);
+        key = ((uint64_t)c << 16) | (uint64_t)r;
+      }
+      // group minimum of (cost, rank): lowest rank on ties
+      uint64_t gm = wave_min(key);
+      if (wpg > 1) {
+        if (lane == 0) s_wmin[wave] = gm;
+        __syncthreads();
+        gm = ~0ull;
+        for (int i = 0; i < wpg; ++i) gm = min(gm, s_wmin[g * wpg + i]);
+      }
+      if (active && key == gm) {
+        for (int d = 0; d < k; ++d) {
+          const int b = (int)((locs >> (6 * d)) & 63u);
+          s_loc[g * kMaxSubset + d] = (int)__popcll(u & ((1ull << b) - 1ull));
+        }
+        uint64_t uu = u;
+        int rr = 0;
+        while (uu) {
+          const int b = __builtin_ctzll(uu);
+          uu &= uu - 1;
+          s_typ[g * kMaxSubset + rr] = pk.type_of(b, s_caps, n);
+          ++rr;
+        }
+        s_u[g] = rr;
+        s_cst[g] = c;
+      }
+      if (r == 0 && k == 0) {
+        s_u[g] = 0;
+        s_cst[g] = 0;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int32_t run = carry;
+        for (int i = 0; i < spr; ++i) {
+          s_base[i] = run;
+          run += s_u[i];
+          cost_acc += s_cst[i];
+        }
+        carry = run;
+      }
+      __syncthreads();
+      if (r < k) {
+        a.assign[off + s_item[g * kMaxSubset + r]] = s_base[g] + s_loc[g * kMaxSubset + r];
+      }
+      if (r < s_u[g] && k > 0) {
+        a.types[off + s_base[g] + r] = s_typ[g * kMaxSubset + r];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      a.nbins[inst] = carry;
+      a.cost[inst] = cost_acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename Kern>
+hipError_t raise_lds(Kern kern, size_t lds) {
+  if (lds > 65536) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  return hipSuccess;
+}
+
+// minimum (cost, index) over num costs, lowest index on ties
+__global__ void __launch_bounds__(1024) k_best_of(const int64_t* cost, int32_t num, int64_t* out) {
+  __shared__ int64_t sc[1024];
+  __shared__ int64_t si[1024];
+  int64_t bc = 0x7FFFFFFFFFFFFFFFll, bi = 0x7FFFFFFFFFFFFFFFll;
+  for (int i = threadIdx.x; i < num; i += blockDim.x) {
+    const int64_t c = cost[i];
+    if (c < bc) {
+      bc = c;
+      bi = i;
+    }
+  }
+  sc[threadIdx.x] = bc;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int st = blockDim.x >> 1; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      const int64_t c2 = sc[threadIdx.x + st], i2 = si[threadIdx.x + st];
+      if (c2 < sc[threadIdx.x] || (c2 == sc[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sc[threadIdx.x] = c2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = num > 0 ? sc[0] : -1;
+    out[1] = num > 0 ? si[0] : -1;
+  }
+}
+
+}  // namespace
+
+
+size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide) {
+  return (size_t)block * ((wide ? 2 : 1) * 4 * (size_t)nbslots + 4 * (size_t)s1 + (size_t)s1);
+}
+
+int h2_group(int s2) {
+  int fact = 1;
+  for (int i = 2; i <= s2; ++i) fact *= i;
+  return ((fact + 63) / 64) * 64;
+}
+
+size_t h2_lds_bytes(int nbslots, int block, int group, bool wide) {
+  const int spr = block / group;
+  return (size_t)block * (wide ? 2 : 1) * 4 * (size_t)nbslots +
+         (size_t)spr * (4 * kMaxSubset * 4 + 2 * 4) + (size_t)spr * 8;
+}
+
+
+hipError_t launch_h1(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
+  if (a.num <= 0) return hipSuccess;
+  const size_t lds = h1_lds_bytes(nbslots, a.s1, block, wide);
+  hipError_t e;
+  if (!wide) {
+    e = raise_lds(k_h1<uint32_t>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_h1<uint32_t>, dim3(a.num), dim3(block), lds, s, a, nbslots);
+  } else {
+    e = raise_lds(k_h1<uint64_t>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_h1<uint64_t>, dim3(a.num), dim3(block), lds, s, a, nbslots);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_h2(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
+  if (a.num <= 0) return hipSuccess;
+  const int group = h2_group(a.s2);
+  if (block < group) block = group;
+  block = (block / group) * group;
+  const size_t lds = h2_lds_bytes(nbslots, block, group, wide);
+  hipError_t e;
+  if (!wide) {
+    e = raise_lds(k_h2<uint32_t>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_h2<uint32_t>, dim3(a.num), dim3(block), lds, s, a, nbslots, group);
+  } else {
+    e = raise_lds(k_h2<uint64_t>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_h2<uint64_t>, dim3(a.num), dim3(block), lds, s, a, nbslots, group);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_best_of, dim3(1), dim3(1024), 0, s, cost, num, out);
+  return hipGetLastError();
+}
+
+}  // namespace vsbpp

@@ -1,0 +1,51 @@
+// Kernel-side argument block and launch entry points shared by the C-ABI
+// host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vsbpp {
+
+// error codes written to nbins[i] for instances that fail device-side checks
+// (same values as the public VSBPP_E_* codes)
+constexpr int32_t kErrSize = -2, kErrCaps = -3, kErrWeight = -4, kErrOption = -6;
+
+constexpr int kMaxTypes = 16;
+
+struct BatchArgs {
+  const int32_t* w;         // CSR weights
+  const int64_t* item_off;  // [num+1]
+  const int32_t* caps;      // CSR capacities, strictly decreasing per instance
+  const int32_t* cap_off;   // [num+1]
+  const int32_t* order;     // optional CSR ordering (local item ids), or null
+  const uint64_t* seeds;    // optional per-instance generator keys, or null
+  uint64_t seed;            // key used when seeds is null
+  int32_t* assign;          // [sum m]
+  int32_t* types;           // [sum m]
+  int32_t* nbins;           // [num]
+  int64_t* cost;            // [num]
+  int32_t num;              // instances
+  int32_t max_items;        // per-instance bound guaranteed by the caller
+  int32_t max_cap;          // bound on B_1 guaranteed by the caller
+  int32_t max_types;        // bound on n guaranteed by the caller
+  int32_t type_rule;        // 0 smallest fit, 1 largest
+  int32_t force_crit;       // -1 or 0/1/2 (H1/H2 only)
+  int32_t s1;               // H1 items per sublist
+  int32_t s2;               // H2 subset size
+  int32_t slots;            // plain kernel: LDS key slots per wavefront
+};
+
+// Launch helpers (defined next to their kernels).  They return a hipError_t.
+hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int waves_per_block,
+                        size_t lds_per_wave, hipStream_t s);
+size_t plain_lds_per_wave(int slots, int max_items, bool wide);
+size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide);
+size_t h2_lds_bytes(int nbslots, int block, int group, bool wide);
+int h2_group(int s2);
+hipError_t launch_h1(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
+                     hipStream_t s);
+hipError_t launch_h2(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
+                     hipStream_t s);
+hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStream_t s);
+
+}  // namespace vsbpp

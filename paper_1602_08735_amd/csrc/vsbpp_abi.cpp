@@ -1,0 +1,319 @@
+// C-ABI entry points: argument checks, launch planning and the synchronous
+// host-pointer path.  Every packing step runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/vsbpp.h"
+#include "kernels.h"
+
+namespace {
+
+using vsbpp::BatchArgs;
+
+int32_t check_instance(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                       int32_t heuristic, const vsbpp_options& o, bool check_order) {
+  if (!w || !caps) return VSBPP_E_NULL;
+  if (m < 1 || n < 1 || n > vsbpp::kMaxTypes) return VSBPP_E_SIZE;
+  for (int32_t k = 0; k < n; ++k) {
+    if (caps[k] <= 0) return VSBPP_E_CAPS;
+    if (k > 0 && caps[k] >= caps[k - 1]) return VSBPP_E_CAPS;
+  }
+  for (int32_t j = 0; j < m; ++j)
+    if (w[j] < 1 || w[j] > caps[0]) return VSBPP_E_WEIGHT;
+  if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
+  if (check_order && o.order) {
+    std::vector<char> seen((size_t)m, 0);
+    for (int32_t q = 0; q < m; ++q) {
+      const int32_t j = o.order[q];
+      if (j < 0 || j >= m || seen[(size_t)j]) return VSBPP_E_OPTION;
+      seen[(size_t)j] = 1;
+    }
+  }
+  return VSBPP_OK;
+}
+
+int32_t check_options(const vsbpp_options& o) {
+  if (o.h1_items_per_sublist < 1 || o.h1_items_per_sublist > 16) return VSBPP_E_OPTION;
+  if (o.h2_subset_size < 1 || o.h2_subset_size > 6) return VSBPP_E_OPTION;
+  if (o.type_rule != VSBPP_TYPE_SMALLEST_FIT && o.type_rule != VSBPP_TYPE_LARGEST)
+    return VSBPP_E_OPTION;
+  if (o.force_criterion < -1 || o.force_criterion > VSBPP_WF) return VSBPP_E_OPTION;
+  return VSBPP_OK;
+}
+
+vsbpp_options resolve(const vsbpp_options* opt) {
+  vsbpp_options o;
+  vsbpp_options_init(&o);
+  if (opt) {
+    // accept older/shorter option structs: copy what the caller declares
+    size_t sz = opt->struct_size;
+    if (sz == 0 || sz > sizeof(o)) sz = sizeof(o);
+    std::memcpy(&o, opt, sz);
+    o.struct_size = sizeof(o);
+  }
+  return o;
+}
+
+struct DeviceState {
+  bool probed = false;
+  bool ok = false;
+  int max_lds_block = 65536;
+};
+
+std::mutex g_mu;
+DeviceState g_dev;
+
+bool device_ok_locked() {
+  if (!g_dev.probed) {
+    g_dev.probed = true;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+      (void)hipGetLastError();
+      return false;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return false;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+            hipSuccess &&
+        lds > 0)
+      g_dev.max_lds_block = lds;
+    g_dev.ok = true;
+  }
+  return g_dev.ok;
+}
+
+int round_up(int x, int to) { return ((x + to - 1) / to) * to; }
+
+// Plans and launches one batch.  All pointers in `a` are device pointers.
+int32_t launch_batch(BatchArgs a, int32_t heuristic, int32_t max_types, hipStream_t s) {
+  const bool wide = a.max_cap > 0x7FFF || a.max_items > 0xFFFF;
+  hipError_t e = hipSuccess;
+  if (heuristic <= VSBPP_WF) {
+    const int slots = round_up(a.max_items, 256);
+    if (!wide && slots > 65536) return VSBPP_E_SIZE;
+    a.slots = slots;
+    const size_t per_wave = vsbpp::plain_lds_per_wave(slots, a.max_items, wide);
+    int wpb = (int)((size_t)g_dev.max_lds_block / per_wave);
+    if (wpb < 1) return VSBPP_E_SIZE;
+    if (wpb > 4) wpb = 4;
+    e = vsbpp::launch_plain(a, heuristic, wide, wpb, per_wave, s);
+  } else if (heuristic == VSBPP_H1) {
+    const int nbslots = round_up(max_types + 2 * a.s1, 4);
+    const int packers = (a.max_items + a.s1 - 1) / a.s1;
+    int block = round_up(packers, 64);
+    if (block > 256) block = 256;
+    while (block > 64 &&
+           vsbpp::h1_lds_bytes(nbslots, a.s1, block, wide) > (size_t)g_dev.max_lds_block)
+      block -= 64;
+    if (vsbpp::h1_lds_bytes(nbslots, a.s1, block, wide) > (size_t)g_dev.max_lds_block)
+      return VSBPP_E_SIZE;
+    e = vsbpp::launch_h1(a, wide, nbslots, block, s);
+  } else {
+    const int nbslots = round_up(max_types + 2 * a.s2, 4);
+    const int group = vsbpp::h2_group(a.s2);
+    int block = group >= 256 ? group : 256;
+    while (block > group &&
+           vsbpp::h2_lds_bytes(nbslots, block, group, wide) > (size_t)g_dev.max_lds_block)
+      block -= group;
+    if (vsbpp::h2_lds_bytes(nbslots, block, group, wide) > (size_t)g_dev.max_lds_block)
+      return VSBPP_E_SIZE;
+    e = vsbpp::launch_h2(a, wide, nbslots, block, s);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return VSBPP_E_DEVICE;
+  }
+  return VSBPP_OK;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool alloc(size_t n) { return hipMalloc(&p, sizeof(T) * (n ? n : 1)) == hipSuccess; }
+};
+
+}  // namespace
+
+extern "C" {
+
+void vsbpp_options_init(vsbpp_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->struct_size = sizeof(*opt);
+  opt->seed = 0;
+  opt->h1_items_per_sublist = 10;
+  opt->h2_subset_size = 5;
+  opt->type_rule = VSBPP_TYPE_SMALLEST_FIT;
+  opt->force_criterion = -1;
+  opt->order = nullptr;
+}
+
+const char* vsbpp_strerror(int32_t code) {
+  switch (code) {
+    case VSBPP_OK: return "ok";
+    case VSBPP_E_NULL: return "null pointer argument";
+    case VSBPP_E_SIZE: return "size out of range (m, n or a declared bound)";
+    case VSBPP_E_CAPS: return "capacities must be positive and strictly decreasing";
+    case VSBPP_E_WEIGHT: return "weights must lie in [1, B_1]";
+    case VSBPP_E_HEURISTIC: return "unknown heuristic";
+    case VSBPP_E_OPTION: return "invalid option";
+    case VSBPP_E_DEVICE: return "no usable gfx950 device, or a HIP runtime error";
+    case VSBPP_E_NOMEM: return "device memory allocation failed";
+    default: return code >= 0 ? "ok" : "unknown error";
+  }
+}
+
+int32_t vsbpp_device_ok(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return device_ok_locked() ? 1 : 0;
+}
+
+int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capacities, int32_t n,
+                      int32_t heuristic, const vsbpp_options* opt, int32_t* out_assignment,
+                      int32_t* out_bin_types, int64_t* out_cost) {
+  const vsbpp_options o = resolve(opt);
+  if (!out_assignment || !out_bin_types) return VSBPP_E_NULL;
+  int32_t rc = check_instance(weights, m, capacities, n, heuristic, o, true);
+  if (rc != VSBPP_OK) return rc;
+  rc = check_options(o);
+  if (rc != VSBPP_OK) return rc;
+
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!device_ok_locked()) return VSBPP_E_DEVICE;
+
+  DevBuf<int32_t> dw, dc, dord, dassign, dtypes, dnb, dcoff;
+  DevBuf<int64_t> doff, dcost;
+  if (!dw.alloc((size_t)m) || !dc.alloc((size_t)n) || !dassign.alloc((size_t)m) ||
+      !dtypes.alloc((size_t)m) || !dnb.alloc(1) || !dcoff.alloc(2) || !doff.alloc(2) ||
+      !dcost.alloc(1) || (o.order && !dord.alloc((size_t)m)))
+    return VSBPP_E_NOMEM;
+  const int64_t hoff[2] = {0, m};
+  const int32_t hcoff[2] = {0, n};
+  hipStream_t s = nullptr;
+  bool ok = hipMemcpy(dw.p, weights, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(dc.p, capacities, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(doff.p, hoff, sizeof(hoff), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(dcoff.p, hcoff, sizeof(hcoff), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && o.order)
+    ok = hipMemcpy(dord.p, o.order, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice) ==
+         hipSuccess;
+  if (!ok) return VSBPP_E_DEVICE;
+
+  BatchArgs a{};
+  a.w = dw.p;
+  a.item_off = doff.p;
+  a.caps = dc.p;
+  a.cap_off = dcoff.p;
+  a.order = o.order ? dord.p : nullptr;
+  a.seeds = nullptr;
+  a.seed = o.seed;
+  a.assign = dassign.p;
+  a.types = dtypes.p;
+  a.nbins = dnb.p;
+  a.cost = dcost.p;
+  a.num = 1;
+  a.max_items = m;
+  a.max_cap = capacities[0];
+  a.max_types = n;
+  a.type_rule = o.type_rule;
+  a.force_crit = o.force_criterion;
+  a.s1 = o.h1_items_per_sublist;
+  a.s2 = o.h2_subset_size;
+  rc = launch_batch(a, heuristic, n, s);
+  if (rc != VSBPP_OK) return rc;
+  if (hipStreamSynchronize(s) != hipSuccess) return VSBPP_E_DEVICE;
+  int32_t nb = 0;
+  int64_t cost = 0;
+  if (hipMemcpy(&nb, dnb.p, sizeof(nb), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&cost, dcost.p, sizeof(cost), hipMemcpyDeviceToHost) != hipSuccess)
+    return VSBPP_E_DEVICE;
+  if (nb < 0) return nb;
+  std::vector<int32_t> ha((size_t)m), ht((size_t)nb);
+  if (hipMemcpy(ha.data(), dassign.p, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(ht.data(), dtypes.p, sizeof(int32_t) * (size_t)nb, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return VSBPP_E_DEVICE;
+  std::memcpy(out_assignment, ha.data(), sizeof(int32_t) * (size_t)m);
+  std::memcpy(out_bin_types, ht.data(), sizeof(int32_t) * (size_t)nb);
+  if (out_cost) *out_cost = cost;
+  return nb;
+}
+
+int32_t vsbpp_pack(const int32_t* weights, int32_t m, const int32_t* capacities, int32_t n,
+                   int32_t heuristic, int32_t* out_assignment, int32_t* out_bin_types) {
+  return vsbpp_pack_ex(weights, m, capacities, n, heuristic, nullptr, out_assignment,
+                       out_bin_types, nullptr);
+}
+
+int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
+                         const int64_t* d_item_off, const int32_t* d_capacities,
+                         const int32_t* d_cap_off, int32_t max_items, int32_t max_types,
+                         int32_t max_capacity, int32_t heuristic, const vsbpp_options* opt,
+                         const int32_t* d_order, const uint64_t* d_seeds,
+                         int32_t* d_assignment, int32_t* d_bin_types, int32_t* d_nbins,
+                         int64_t* d_cost, void* hip_stream) {
+  const vsbpp_options o = resolve(opt);
+  if (num_instances < 0) return VSBPP_E_SIZE;
+  if (num_instances == 0) return VSBPP_OK;
+  if (!d_weights || !d_item_off || !d_capacities || !d_cap_off || !d_assignment ||
+      !d_bin_types || !d_nbins || !d_cost)
+    return VSBPP_E_NULL;
+  if (max_items < 1 || max_types < 1 || max_types > vsbpp::kMaxTypes || max_capacity < 1)
+    return VSBPP_E_SIZE;
+  if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
+  int32_t rc = check_options(o);
+  if (rc != VSBPP_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!device_ok_locked()) return VSBPP_E_DEVICE;
+  }
+  BatchArgs a{};
+  a.w = d_weights;
+  a.item_off = d_item_off;
+  a.caps = d_capacities;
+  a.cap_off = d_cap_off;
+  a.order = d_order;
+  a.seeds = d_seeds;
+  a.seed = o.seed;
+  a.assign = d_assignment;
+  a.types = d_bin_types;
+  a.nbins = d_nbins;
+  a.cost = d_cost;
+  a.num = num_instances;
+  a.max_items = max_items;
+  a.max_cap = max_capacity;
+  a.max_types = max_types;
+  a.type_rule = o.type_rule;
+  a.force_crit = o.force_criterion;
+  a.s1 = o.h1_items_per_sublist;
+  a.s2 = o.h2_subset_size;
+  return launch_batch(a, heuristic, max_types, (hipStream_t)hip_stream);
+}
+
+int32_t vsbpp_best_of(const int64_t* d_cost, int32_t num, int64_t* d_out, void* hip_stream) {
+  if (!d_cost || !d_out) return VSBPP_E_NULL;
+  if (num < 1) return VSBPP_E_SIZE;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!device_ok_locked()) return VSBPP_E_DEVICE;
+  }
+  if (vsbpp::launch_best_of(d_cost, num, d_out, (hipStream_t)hip_stream) != hipSuccess)
+    return VSBPP_E_DEVICE;
+  return VSBPP_OK;
+}
+
+}  // extern "C"

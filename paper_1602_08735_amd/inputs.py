@@ -86,7 +86,15 @@ def make_batch(weights_list, caps_list, order_list=None, seeds=None, meta=None) 
 
 def _distinct_desc(rng: np.random.Generator, lo: int, hi: int, k: int) -> np.ndarray:
     """k distinct integers from [lo, hi], strictly decreasing."""
-    v = rng.choice(np.arange(lo, hi + 1, dtype=np.int64), size=k, replace=False)
+    if k <= 0:
+        return np.zeros(0, dtype=np.int32)
+    if hi - lo + 1 <= 4096:
+        v = rng.choice(np.arange(lo, hi + 1, dtype=np.int64), size=k, replace=False)
+    else:
+        seen: set = set()
+        while len(seen) < k:
+            seen.add(int(rng.integers(lo, hi + 1)))
+        v = np.array(sorted(seen), dtype=np.int64)
     return np.sort(v)[::-1].astype(np.int32)
 
 
