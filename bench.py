@@ -39,8 +39,11 @@ def parse():
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--items", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--heuristics", default=",".join(HEURISTICS))
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy (outside the timed region) "
+                         "as the known-size reference for HBM traffic counters")
     return ap.parse_args()
 
 
@@ -107,6 +110,12 @@ def main():
             if ev is not None:
                 ev[k][1].record(stream)
 
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
