@@ -154,6 +154,68 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
                          int32_t* d_assignment, int32_t* d_bin_types, int32_t* d_nbins,
                          int64_t* d_cost, void* hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Plans: a batch bound to its buffers, a heuristic and a launch shape, run   */
+/* any number of times.  A plan owns a small device workspace (a work        */
+/* counter and an instance schedule) allocated when it is created, so runs   */
+/* allocate nothing and may be captured into, or replayed from, a HIP graph. */
+/* ------------------------------------------------------------------------ */
+
+/* A device-resident batch: the same CSR layout, bounds and outputs as the
+ * arguments of vsbpp_pack_batch (see there). */
+typedef struct vsbpp_batch {
+  int32_t num_instances;
+  const int32_t* weights;
+  const int64_t* item_off;
+  const int32_t* capacities;
+  const int32_t* cap_off;
+  const int32_t* order;   /* or NULL */
+  const uint64_t* seeds;  /* or NULL */
+  int32_t max_items, max_types, max_capacity;
+  int32_t* assignment;
+  int32_t* bin_types;
+  int32_t* nbins;
+  int64_t* cost;
+} vsbpp_batch;
+
+/* Launch shape.  mode 0: one wavefront (FF/BF/WF) or one workgroup (H1/H2)
+ * per instance, in a grid covering the batch; mode 1: persistent grid of
+ * resident workgroups taking instances from a device work counter.  lpt = 1
+ * processes instances by decreasing item count (largest first, for uneven
+ * batches; batches up to 8192 instances).  waves_per_block: FF/BF/WF
+ * wavefronts (one instance each) per workgroup, 1..4.  block_threads: H1/H2
+ * workgroup size (H2: a multiple of roundup(s2!, 64)). */
+typedef struct vsbpp_launch {
+  int32_t mode;
+  int32_t lpt;
+  int32_t waves_per_block;
+  int32_t block_threads;
+} vsbpp_launch;
+
+enum {
+  VSBPP_PLAN_GRAPH = 1,     /* capture the launch sequence into a hipGraph    */
+  VSBPP_PLAN_AUTOTUNE = 2   /* time the candidate launch shapes on the batch
+                               (running it several times) and keep the
+                               fastest; results are cached per process and,
+                               when the environment variable VSBPP_TUNE_CACHE
+                               names a file, in that file                    */
+};
+
+typedef struct vsbpp_plan vsbpp_plan;
+
+/* Creates a plan.  `launch` (may be NULL) forces a launch shape; otherwise
+ * the shape comes from the tuning cache, from tuning (VSBPP_PLAN_AUTOTUNE)
+ * or from defaults.  Autotuning runs the batch on the device, synchronously.
+ * Returns VSBPP_OK or a negative code; *out is NULL on error. */
+int32_t vsbpp_plan_create(const vsbpp_batch* batch, int32_t heuristic, const vsbpp_options* opt,
+                          const vsbpp_launch* launch, uint32_t flags, vsbpp_plan** out);
+/* Enqueues one run on hip_stream (graph replay when captured). */
+int32_t vsbpp_plan_run(vsbpp_plan* plan, void* hip_stream);
+/* Launch shape the plan uses. */
+int32_t vsbpp_plan_launch(const vsbpp_plan* plan, vsbpp_launch* out);
+/* Releases the plan, its workspace and graph (after outstanding runs). */
+void vsbpp_plan_destroy(vsbpp_plan* plan);
+
 /* Best of a batch: writes d_out[0] = min cost and d_out[1] = the lowest index
  * reaching it over d_cost[0..num-1] (device pointers, asynchronous on
  * hip_stream).  Used to keep the best of several orderings of one instance. */
@@ -161,6 +223,10 @@ int32_t vsbpp_best_of(const int64_t* d_cost, int32_t num, int64_t* d_out, void* 
 
 /* Text of an error code (static storage). */
 const char* vsbpp_strerror(int32_t code);
+
+/* Detail of the last HIP runtime failure reported as VSBPP_E_DEVICE by this
+ * thread (empty if none); static thread-local storage. */
+const char* vsbpp_last_error(void);
 
 /* 1 if a gfx950 device is visible and usable, else 0. */
 int32_t vsbpp_device_ok(void);

@@ -30,14 +30,18 @@ ERRORS = {
 # exported symbols, as declared in include/vsbpp.h
 EXPORTS = (
     "vsbpp_options_init", "vsbpp_pack", "vsbpp_pack_ex", "vsbpp_pack_batch",
-    "vsbpp_best_of", "vsbpp_strerror", "vsbpp_device_ok",
+    "vsbpp_best_of", "vsbpp_strerror", "vsbpp_device_ok", "vsbpp_plan_create",
+    "vsbpp_plan_run", "vsbpp_plan_launch", "vsbpp_plan_destroy", "vsbpp_last_error",
 )
 
 
 class VsbppError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = int(code)
-        super().__init__(f"{what}: {ERRORS.get(self.code, self.code)} ({self.code})")
+        detail = ""
+        if self.code == -7 and _lib is not None:
+            detail = " " + _lib.vsbpp_last_error().decode()
+        super().__init__(f"{what}: {ERRORS.get(self.code, self.code)} ({self.code}){detail}")
 
 
 class Options(ctypes.Structure):
@@ -79,6 +83,8 @@ def lib():
         L.vsbpp_best_of.argtypes = [vp, i32, vp, vp]
         L.vsbpp_strerror.restype = ctypes.c_char_p
         L.vsbpp_strerror.argtypes = [i32]
+        L.vsbpp_last_error.restype = ctypes.c_char_p
+        L.vsbpp_last_error.argtypes = []
         L.vsbpp_device_ok.restype = i32
         L.vsbpp_device_ok.argtypes = []
         _lib = L
@@ -196,3 +202,101 @@ def best_of(cost_tensor, num: int, out_tensor, stream=None) -> None:
                              ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise VsbppError(rc, "vsbpp_best_of")
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("lpt", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("block_threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("num_instances", ctypes.c_int32),
+        ("weights", ctypes.c_void_p), ("item_off", ctypes.c_void_p),
+        ("capacities", ctypes.c_void_p), ("cap_off", ctypes.c_void_p),
+        ("order", ctypes.c_void_p), ("seeds", ctypes.c_void_p),
+        ("max_items", ctypes.c_int32), ("max_types", ctypes.c_int32),
+        ("max_capacity", ctypes.c_int32),
+        ("assignment", ctypes.c_void_p), ("bin_types", ctypes.c_void_p),
+        ("nbins", ctypes.c_void_p), ("cost", ctypes.c_void_p),
+    ]
+
+
+PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
+
+
+def _plan_lib():
+    L = lib()
+    if not getattr(L, "_plan_ready", False):
+        L.vsbpp_plan_create.restype = ctypes.c_int32
+        L.vsbpp_plan_create.argtypes = [ctypes.POINTER(_BatchDesc), ctypes.c_int32,
+                                        ctypes.POINTER(Options), ctypes.POINTER(Launch),
+                                        ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]
+        L.vsbpp_plan_run.restype = ctypes.c_int32
+        L.vsbpp_plan_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.vsbpp_plan_launch.restype = ctypes.c_int32
+        L.vsbpp_plan_launch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Launch)]
+        L.vsbpp_plan_destroy.restype = None
+        L.vsbpp_plan_destroy.argtypes = [ctypes.c_void_p]
+        L._plan_ready = True
+    return L
+
+
+class Plan:
+    """A DeviceBatch bound to a heuristic and a launch shape (vsbpp_plan_*).
+    The DeviceBatch must outlive the plan."""
+
+    def __init__(self, db: DeviceBatch, heuristic, *, launch: dict | None = None,
+                 graph: bool = False, autotune: bool = False, seed: int = 0, s1: int = 10,
+                 s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
+                 use_order: bool = True, use_seeds: bool = True):
+        L = _plan_lib()
+        ptr = lambda x: None if x is None else x.data_ptr()
+        self.db = db
+        self._desc = _BatchDesc(
+            db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
+            ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
+            db.max_items, db.max_types, db.max_cap,
+            ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
+        o = options(seed, s1, s2, type_rule, force_crit)
+        lp = None
+        if launch is not None:
+            lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
+                        launch.get("waves_per_block", 4), launch.get("block_threads", 256))
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        h = ctypes.c_void_p()
+        rc = L.vsbpp_plan_create(ctypes.byref(self._desc), _heur(heuristic), ctypes.byref(o),
+                                 ctypes.byref(lp) if lp is not None else None, flags,
+                                 ctypes.byref(h))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_plan_create")
+        self._h = h
+
+    def run(self, stream=None) -> None:
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = _plan_lib().vsbpp_plan_run(self._h, ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_plan_run")
+
+    def launch(self) -> dict:
+        out = Launch()
+        rc = _plan_lib().vsbpp_plan_launch(self._h, ctypes.byref(out))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_plan_launch")
+        return out.as_dict()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _plan_lib().vsbpp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

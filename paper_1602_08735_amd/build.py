@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvsbpp.so")
-SOURCES = ["vsbpp_abi.cpp", "plain_kernel.hip", "hps_kernels.hip"]
-HEADERS = ["device_common.h", "kernels.h"]
+SOURCES = ["vsbpp_abi.cpp", "plan.cpp", "plain_kernel.hip", "hps_kernels.hip"]
+HEADERS = ["device_common.h", "kernels.h", "host_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,41 @@
+// Host-side runtime shared by the C-ABI entry points: device probing, launch
+// shapes and the enqueue sequence of one batch run.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace vsbpp {
+
+struct DevInfo {
+  bool probed = false;
+  bool ok = false;
+  int max_lds_block = 65536;
+  int cus = 1;
+};
+
+// Probes the current device once (thread-safe); ok is false without a gfx950.
+const DevInfo& device_info();
+
+struct LaunchCfg {
+  int mode = 0;   // 0 grid over the batch, 1 persistent
+  int lpt = 0;    // largest instances first
+  int wpb = 4;    // FF/BF/WF wavefronts per workgroup
+  int block = 256;  // H1/H2 workgroup size
+};
+
+// Shape-independent checks of a launch configuration for a batch; returns a
+// VSBPP_E_* code or 0.
+int32_t check_cfg(const LaunchCfg& c, int heuristic, const BatchArgs& a);
+LaunchCfg default_cfg(int heuristic, const BatchArgs& a);
+std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a);
+
+// Enqueues one run: [queue reset] [LPT schedule] pack kernel.  `queue` and
+// `sched` are device workspace (may be null when the configuration needs
+// neither).  Returns a VSBPP_* code.
+int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* queue,
+                      int32_t* sched, hipStream_t s);
+
+}  // namespace vsbpp

@@ -226,6 +226,21 @@ __device__ int validate_block(const BatchArgs& a, int inst, int64_t off, int m, 
   return 0;
 }
 
+// next instance slot of this workgroup: static stride, or the global work
+// counter in persistent mode (thread 0 takes it and broadcasts through LDS)
+__device__ __forceinline__ int next_slot(const BatchArgs& a, int* cursor, int* s_slot) {
+  if (a.queue) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int v = *s_slot;
+    __syncthreads();
+    return v;
+  }
+  const int v = *cursor;
+  *cursor += gridDim.x;
+  return v;
+}
+
 __device__ __forceinline__ uint64_t inst_seed(const BatchArgs& a, int inst) {
   return a.seeds ? a.seeds[inst] : a.seed;
 }
@@ -252,7 +267,12 @@ __global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
   pk.cap = lcap + 4 * tid;
   pk.stride = 4 * B;
 
-  for (int inst = blockIdx.x; inst < a.num; inst += gridDim.x) {
+  __shared__ int s_slot;
+  int cursor = blockIdx.x;
+  for (;;) {
+    const int slot = next_slot(a, &cursor, &s_slot);
+    if (slot >= a.num) break;
+    const int inst = a.sched ? a.sched[slot] : slot;
     const int64_t off = a.item_off[inst];
     const int64_t m64 = a.item_off[inst + 1] - off;
     const int c0 = a.cap_off[inst];
@@ -379,7 +399,12 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
   const int g = tid / group, r = tid - g * group;
   const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
 
-  for (int inst = blockIdx.x; inst < a.num; inst += gridDim.x) {
+  __shared__ int s_slot;
+  int cursor = blockIdx.x;
+  for (;;) {
+    const int slot = next_slot(a, &cursor, &s_slot);
+    if (slot >= a.num) break;
+    const int inst = a.sched ? a.sched[slot] : slot;
     const int64_t off = a.item_off[inst];
     const int64_t m64 = a.item_off[inst + 1] - off;
     const int c0 = a.cap_off[inst];
@@ -494,10 +519,11 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 }
 
 template <typename Kern>
-hipError_t raise_lds(Kern kern, size_t lds) {
-  if (lds > 65536) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+hipError_t raise_lds(Kern kern, size_t lds, bool& done) {
+  if (lds > 65536 && !done) {
+    const hipError_t e = allow_max_dynamic_lds(kern);
+    if (e != hipSuccess) return e;
+    done = true;
   }
   return hipSuccess;
 }
@@ -553,38 +579,121 @@ size_t h2_lds_bytes(int nbslots, int block, int group, bool wide) {
 }
 
 
-hipError_t launch_h1(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
+hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nbslots, int block, int grid,
+                          hipStream_t s) {
   if (a.num <= 0) return hipSuccess;
   const size_t lds = h1_lds_bytes(nbslots, a.s1, block, wide);
+  const int blocks = grid > 0 ? grid : a.num;
   hipError_t e;
   if (!wide) {
-    e = raise_lds(k_h1<uint32_t>, lds);
+    { static bool done1 = false; e = raise_lds(k_h1<uint32_t>, lds, done1); }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h1<uint32_t>, dim3(a.num), dim3(block), lds, s, a, nbslots);
+    hipLaunchKernelGGL(k_h1<uint32_t>, dim3(blocks), dim3(block), lds, s, a, nbslots);
   } else {
-    e = raise_lds(k_h1<uint64_t>, lds);
+    { static bool done2 = false; e = raise_lds(k_h1<uint64_t>, lds, done2); }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h1<uint64_t>, dim3(a.num), dim3(block), lds, s, a, nbslots);
+    hipLaunchKernelGGL(k_h1<uint64_t>, dim3(blocks), dim3(block), lds, s, a, nbslots);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_h2(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
+hipError_t launch_h1(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
+  return launch_h1_grid(a, wide, nbslots, block, 0, s);
+}
+
+hipError_t launch_h2_grid(const BatchArgs& a, bool wide, int nbslots, int block, int grid,
+                          hipStream_t s) {
   if (a.num <= 0) return hipSuccess;
   const int group = h2_group(a.s2);
   if (block < group) block = group;
   block = (block / group) * group;
   const size_t lds = h2_lds_bytes(nbslots, block, group, wide);
+  const int blocks = grid > 0 ? grid : a.num;
   hipError_t e;
   if (!wide) {
-    e = raise_lds(k_h2<uint32_t>, lds);
+    { static bool done3 = false; e = raise_lds(k_h2<uint32_t>, lds, done3); }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h2<uint32_t>, dim3(a.num), dim3(block), lds, s, a, nbslots, group);
+    hipLaunchKernelGGL(k_h2<uint32_t>, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
   } else {
-    e = raise_lds(k_h2<uint64_t>, lds);
+    { static bool done4 = false; e = raise_lds(k_h2<uint64_t>, lds, done4); }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h2<uint64_t>, dim3(a.num), dim3(block), lds, s, a, nbslots, group);
+    hipLaunchKernelGGL(k_h2<uint64_t>, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_h2(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
+  return launch_h2_grid(a, wide, nbslots, block, 0, s);
+}
+
+namespace {
+template <typename Kern>
+int occ(Kern kern, int block, size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+}  // namespace
+
+int h1_blocks_per_cu(bool wide, int block, size_t lds) {
+  return wide ? occ(k_h1<uint64_t>, block, lds) : occ(k_h1<uint32_t>, block, lds);
+}
+
+int h2_blocks_per_cu(bool wide, int block, size_t lds) {
+  return wide ? occ(k_h2<uint64_t>, block, lds) : occ(k_h2<uint32_t>, block, lds);
+}
+
+namespace {
+__global__ void k_queue_reset(int32_t* q) {
+  if (threadIdx.x == 0) *q = 0;
+}
+
+// Instances by decreasing item count, ties by index (bitonic sort of 64-bit
+// keys in LDS, one workgroup; num <= kLptMax).
+__global__ void __launch_bounds__(1024) k_lpt(const int64_t* item_off, int32_t num, int32_t* sched) {
+  __shared__ uint64_t keys[kLptMax];
+  int P = 1;
+  while (P < num) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    uint64_t k = ~0ull;
+    if (i < num) {
+      int64_t m = item_off[i + 1] - item_off[i];
+      if (m < 0) m = 0;
+      if (m > 0x7FFFFFFF) m = 0x7FFFFFFF;
+      k = ((uint64_t)(0xFFFFFFFFu - (uint32_t)m) << 32) | (uint32_t)i;
+    }
+    keys[i] = k;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = keys[i], y = keys[ixj];
+          const bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            keys[i] = y;
+            keys[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < num; i += blockDim.x) sched[i] = (int32_t)(keys[i] & 0xFFFFFFFFu);
+}
+}  // namespace
+
+hipError_t launch_queue_reset(int32_t* queue, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_lpt_schedule(const int64_t* item_off, int32_t num, int32_t* sched,
+                               hipStream_t s) {
+  if (num <= 0 || num > kLptMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lpt, dim3(1), dim3(1024), 0, s, item_off, num, sched);
   return hipGetLastError();
 }
 

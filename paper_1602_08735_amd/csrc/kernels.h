@@ -33,7 +33,33 @@ struct BatchArgs {
   int32_t s1;               // H1 items per sublist
   int32_t s2;               // H2 subset size
   int32_t slots;            // plain kernel: LDS key slots per wavefront
+  int32_t* queue;           // persistent mode: work counter (zeroed before the launch), or null
+  const int32_t* sched;     // optional processing order of the instances (LPT), or null
 };
+
+// Next instance for a wavefront (plain kernel) or a workgroup (H1/H2): a
+// static stride over the grid, or a global work counter in persistent mode.
+// `slot` is a per-caller cursor for the static mode.
+
+// Lets `kern` use all of the device's LDS per workgroup that its own static
+// LDS leaves free (needed above 64 KiB of dynamic LDS); once per kernel.
+template <typename Kern>
+hipError_t allow_max_dynamic_lds(Kern kern) {
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern));
+  if (e != hipSuccess) return e;
+  int dev = 0, maxb = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&maxb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             maxb - (int)fa.sharedSizeBytes);
+}
+
+// LDS budget reserved for the static LDS of the H1/H2 kernels
+constexpr int kStaticLdsReserve = 1024;
 
 // Launch helpers (defined next to their kernels).  They return a hipError_t.
 hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int waves_per_block,
@@ -47,5 +73,23 @@ hipError_t launch_h1(const BatchArgs& a, bool wide, int nb_regs, int block_threa
 hipError_t launch_h2(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
                      hipStream_t s);
 hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStream_t s);
+
+// scheduling helpers
+hipError_t launch_queue_reset(int32_t* queue, hipStream_t s);
+// instances sorted by decreasing item count (ties by index); num <= kLptMax
+constexpr int kLptMax = 8192;
+hipError_t launch_lpt_schedule(const int64_t* item_off, int32_t num, int32_t* sched, hipStream_t s);
+
+// launch shapes; grid = 0 means one wavefront/workgroup per instance
+hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int waves_per_block,
+                             size_t lds_per_wave, int grid, hipStream_t s);
+hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
+                          int grid, hipStream_t s);
+hipError_t launch_h2_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
+                          int grid, hipStream_t s);
+// resident workgroups per CU for a launch shape (for persistent grids)
+int plain_blocks_per_cu(int crit, bool wide, int waves_per_block, size_t lds_per_wave);
+int h1_blocks_per_cu(bool wide, int block_threads, size_t lds);
+int h2_blocks_per_cu(bool wide, int block_threads, size_t lds);
 
 }  // namespace vsbpp

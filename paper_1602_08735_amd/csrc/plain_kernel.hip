@@ -140,7 +140,19 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   Pid* pid = reinterpret_cast<Pid*>(base + (size_t)a.slots * sizeof(K));
   int32_t* smin = reinterpret_cast<int32_t*>(base + (size_t)a.slots * sizeof(K) + pid_bytes);
 
-  for (int inst = blockIdx.x * wpb + wave; inst < a.num; inst += gridDim.x * wpb) {
+  int cursor = blockIdx.x * wpb + wave;
+  for (;;) {
+    int slot;
+    if (a.queue) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(a.queue, 1);
+      slot = uniform(readlane(v, 0));
+    } else {
+      slot = cursor;
+      cursor += gridDim.x * wpb;
+    }
+    if (slot >= a.num) break;
+    const int inst = a.sched ? uniform(a.sched[slot]) : slot;
     const int64_t off = a.item_off[inst];
     const int64_t m64 = a.item_off[inst + 1] - off;
     const int c0 = a.cap_off[inst];
@@ -298,19 +310,27 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
 }
 
 template <int CRIT, typename K>
-hipError_t launch_one(const BatchArgs& a, int wpb, size_t lds_per_wave, hipStream_t s) {
+hipError_t launch_one(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid, hipStream_t s) {
   const size_t lds = lds_per_wave * (size_t)wpb;
   auto kern = k_plain<CRIT, K>;
   static bool raised = false;
   if (lds > 65536 && !raised) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_max_dynamic_lds(kern);
     if (e != hipSuccess) return e;
     raised = true;
   }
-  const int blocks = (a.num + wpb - 1) / wpb;
+  const int blocks = grid > 0 ? grid : (a.num + wpb - 1) / wpb;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, a, wpb, (int)lds_per_wave);
   return hipGetLastError();
+}
+
+template <int CRIT, typename K>
+int occupancy(int wpb, size_t lds_per_wave) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K>, 64 * wpb,
+                                                    lds_per_wave * (size_t)wpb) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
 }
 
 }  // namespace
@@ -324,17 +344,33 @@ size_t plain_lds_per_wave(int slots, int max_items, bool wide) {
   return b;
 }
 
-hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave,
-                        hipStream_t s) {
+hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
+                             size_t lds_per_wave, int grid, hipStream_t s) {
   if (a.num <= 0) return hipSuccess;
   if (!wide) {
-    if (crit == FF) return launch_one<FF, uint32_t>(a, wpb, lds_per_wave, s);
-    if (crit == BF) return launch_one<BF, uint32_t>(a, wpb, lds_per_wave, s);
-    return launch_one<WF, uint32_t>(a, wpb, lds_per_wave, s);
+    if (crit == FF) return launch_one<FF, uint32_t>(a, wpb, lds_per_wave, grid, s);
+    if (crit == BF) return launch_one<BF, uint32_t>(a, wpb, lds_per_wave, grid, s);
+    return launch_one<WF, uint32_t>(a, wpb, lds_per_wave, grid, s);
   }
-  if (crit == FF) return launch_one<FF, uint64_t>(a, wpb, lds_per_wave, s);
-  if (crit == BF) return launch_one<BF, uint64_t>(a, wpb, lds_per_wave, s);
-  return launch_one<WF, uint64_t>(a, wpb, lds_per_wave, s);
+  if (crit == FF) return launch_one<FF, uint64_t>(a, wpb, lds_per_wave, grid, s);
+  if (crit == BF) return launch_one<BF, uint64_t>(a, wpb, lds_per_wave, grid, s);
+  return launch_one<WF, uint64_t>(a, wpb, lds_per_wave, grid, s);
+}
+
+hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave,
+                        hipStream_t s) {
+  return launch_plain_grid(a, crit, wide, wpb, lds_per_wave, 0, s);
+}
+
+int plain_blocks_per_cu(int crit, bool wide, int wpb, size_t lds_per_wave) {
+  if (!wide) {
+    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lds_per_wave);
+    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lds_per_wave);
+    return occupancy<WF, uint32_t>(wpb, lds_per_wave);
+  }
+  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lds_per_wave);
+  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lds_per_wave);
+  return occupancy<WF, uint64_t>(wpb, lds_per_wave);
 }
 
 }  // namespace vsbpp

@@ -1,0 +1,276 @@
+// Plans: a device batch bound to a heuristic and a launch shape, with its
+// own workspace (work counter + instance schedule), optional HIP-graph
+// capture and an autotuner over launch shapes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/vsbpp.h"
+#include "host_internal.h"
+#include "kernels.h"
+
+namespace vsbpp {
+int32_t check_options_public(const vsbpp_options& o);
+vsbpp_options resolve_options(const vsbpp_options* opt);
+}  // namespace vsbpp
+
+struct vsbpp_plan {
+  vsbpp::BatchArgs args{};
+  int heuristic = 0;
+  vsbpp::LaunchCfg cfg;
+  int32_t* workspace = nullptr;  // [0] work counter, [1..num] schedule
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, vsbpp::LaunchCfg> g_tune;
+bool g_tune_loaded = false;
+
+int bucket(long long x) {
+  int b = 0;
+  while ((1ll << b) < x) ++b;
+  return b;
+}
+
+std::string tune_key(int heuristic, const vsbpp::BatchArgs& a) {
+  std::ostringstream k;
+  k << "h" << heuristic << "-m" << bucket(a.max_items) << "-t" << a.max_types << "-c"
+    << (a.max_cap > 0x7FFF ? 1 : 0) << "-n" << bucket(a.num) << "-s"
+    << (heuristic == VSBPP_H1 ? a.s1 : heuristic == VSBPP_H2 ? a.s2 : 0);
+  return k.str();
+}
+
+const char* cache_path() {
+  const char* p = std::getenv("VSBPP_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void load_cache_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* p = cache_path();
+  if (!p) return;
+  std::ifstream f(p);
+  std::string key;
+  vsbpp::LaunchCfg c;
+  while (f >> key >> c.mode >> c.lpt >> c.wpb >> c.block) g_tune[key] = c;
+}
+
+void store_cache_locked() {
+  const char* p = cache_path();
+  if (!p) return;
+  std::ofstream f(p, std::ios::trunc);
+  for (const auto& kv : g_tune)
+    f << kv.first << " " << kv.second.mode << " " << kv.second.lpt << " " << kv.second.wpb << " "
+      << kv.second.block << "\n";
+}
+
+int32_t run_eager(vsbpp_plan* p, hipStream_t s) {
+  return vsbpp::enqueue_batch(p->args, p->heuristic, p->cfg, p->workspace, p->workspace + 1, s);
+}
+
+// Times every candidate shape on the batch itself and returns the fastest.
+int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
+  hipStream_t s = nullptr;
+  if (hipStreamCreate(&s) != hipSuccess) return VSBPP_E_DEVICE;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return VSBPP_E_DEVICE;
+  }
+  float best_ms = 1e30f;
+  int32_t rc = VSBPP_OK;
+  bool found = false;
+  for (const vsbpp::LaunchCfg& c : vsbpp::candidate_cfgs(p->heuristic, p->args)) {
+    p->cfg = c;
+    rc = run_eager(p, s);  // warm-up
+    if (rc == VSBPP_E_SIZE || rc == VSBPP_E_OPTION) continue;
+    if (rc != VSBPP_OK) break;
+    float t[3];
+    for (float& ti : t) {
+      (void)hipEventRecord(e0, s);
+      rc = run_eager(p, s);
+      (void)hipEventRecord(e1, s);
+      if (rc != VSBPP_OK || hipEventSynchronize(e1) != hipSuccess) {
+        rc = rc != VSBPP_OK ? rc : VSBPP_E_DEVICE;
+        break;
+      }
+      (void)hipEventElapsedTime(&ti, e0, e1);
+    }
+    if (rc != VSBPP_OK) break;
+    std::sort(t, t + 3);
+    if (t[1] < best_ms) {
+      best_ms = t[1];
+      *best = c;
+      found = true;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (rc != VSBPP_OK) return rc;
+  return found ? VSBPP_OK : VSBPP_E_SIZE;
+}
+
+int32_t capture(vsbpp_plan* p) {
+  hipStream_t s = nullptr;
+  if (hipStreamCreate(&s) != hipSuccess) return VSBPP_E_DEVICE;
+  // one eager run first, so one-time function attributes are set outside capture
+  int32_t rc = run_eager(p, s);
+  if (rc == VSBPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = VSBPP_E_DEVICE;
+  if (rc == VSBPP_OK) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = VSBPP_E_DEVICE;
+    } else {
+      rc = run_eager(p, s);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      if (rc == VSBPP_OK && e != hipSuccess) rc = VSBPP_E_DEVICE;
+      if (rc == VSBPP_OK) {
+        p->graph = g;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess)
+          rc = VSBPP_E_DEVICE;
+      } else if (g) {
+        (void)hipGraphDestroy(g);
+      }
+    }
+  }
+  (void)hipGetLastError();
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vsbpp_plan_create(const vsbpp_batch* b, int32_t heuristic, const vsbpp_options* opt,
+                          const vsbpp_launch* launch, uint32_t flags, vsbpp_plan** out) {
+  if (!out) return VSBPP_E_NULL;
+  *out = nullptr;
+  if (!b) return VSBPP_E_NULL;
+  if (b->num_instances < 1) return VSBPP_E_SIZE;
+  if (!b->weights || !b->item_off || !b->capacities || !b->cap_off || !b->assignment ||
+      !b->bin_types || !b->nbins || !b->cost)
+    return VSBPP_E_NULL;
+  if (b->max_items < 1 || b->max_types < 1 || b->max_types > vsbpp::kMaxTypes ||
+      b->max_capacity < 1)
+    return VSBPP_E_SIZE;
+  if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
+  const vsbpp_options o = vsbpp::resolve_options(opt);
+  int32_t rc = vsbpp::check_options_public(o);
+  if (rc != VSBPP_OK) return rc;
+  if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
+
+  vsbpp_plan* p = new vsbpp_plan;
+  vsbpp::BatchArgs& a = p->args;
+  a.w = b->weights;
+  a.item_off = b->item_off;
+  a.caps = b->capacities;
+  a.cap_off = b->cap_off;
+  a.order = b->order;
+  a.seeds = b->seeds;
+  a.seed = o.seed;
+  a.assign = b->assignment;
+  a.types = b->bin_types;
+  a.nbins = b->nbins;
+  a.cost = b->cost;
+  a.num = b->num_instances;
+  a.max_items = b->max_items;
+  a.max_cap = b->max_capacity;
+  a.max_types = b->max_types;
+  a.type_rule = o.type_rule;
+  a.force_crit = o.force_criterion;
+  a.s1 = o.h1_items_per_sublist;
+  a.s2 = o.h2_subset_size;
+  p->heuristic = heuristic;
+
+  if (hipMalloc(&p->workspace, sizeof(int32_t) * ((size_t)a.num + 1)) != hipSuccess) {
+    delete p;
+    return VSBPP_E_NOMEM;
+  }
+  if (launch) {
+    p->cfg.mode = launch->mode;
+    p->cfg.lpt = launch->lpt;
+    p->cfg.wpb = launch->waves_per_block;
+    p->cfg.block = launch->block_threads;
+    rc = vsbpp::check_cfg(p->cfg, heuristic, a);
+  } else {
+    const std::string key = tune_key(heuristic, a);
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      load_cache_locked();
+      auto it = g_tune.find(key);
+      if (it != g_tune.end() && vsbpp::check_cfg(it->second, heuristic, a) == VSBPP_OK) {
+        p->cfg = it->second;
+        have = true;
+      }
+    }
+    if (!have && (flags & VSBPP_PLAN_AUTOTUNE)) {
+      vsbpp::LaunchCfg best;
+      rc = autotune(p, &best);
+      if (rc == VSBPP_OK) {
+        p->cfg = best;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+        store_cache_locked();
+      }
+    } else if (!have) {
+      p->cfg = vsbpp::default_cfg(heuristic, a);
+    }
+  }
+  if (rc == VSBPP_OK && (flags & VSBPP_PLAN_GRAPH)) rc = capture(p);
+  if (rc != VSBPP_OK) {
+    vsbpp_plan_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return VSBPP_OK;
+}
+
+int32_t vsbpp_plan_run(vsbpp_plan* p, void* hip_stream) {
+  if (!p) return VSBPP_E_NULL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (p->exec) {
+    if (hipGraphLaunch(p->exec, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return VSBPP_E_DEVICE;
+    }
+    return VSBPP_OK;
+  }
+  return run_eager(p, s);
+}
+
+int32_t vsbpp_plan_launch(const vsbpp_plan* p, vsbpp_launch* out) {
+  if (!p || !out) return VSBPP_E_NULL;
+  out->mode = p->cfg.mode;
+  out->lpt = p->cfg.lpt;
+  out->waves_per_block = p->cfg.wpb;
+  out->block_threads = p->cfg.block;
+  return VSBPP_OK;
+}
+
+void vsbpp_plan_destroy(vsbpp_plan* p) {
+  if (!p) return;
+  if (p->exec || p->workspace) (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->workspace) (void)hipFree(p->workspace);
+  delete p;
+}
+
+}  // extern "C"

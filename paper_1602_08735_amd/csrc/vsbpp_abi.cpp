@@ -2,17 +2,28 @@
 // host-pointer path.  Every packing step runs in the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
 
 #include "../../include/vsbpp.h"
+#include "host_internal.h"
 #include "kernels.h"
 
 namespace {
 
 using vsbpp::BatchArgs;
+
+}  // namespace
+
+namespace vsbpp {
+int32_t check_options_public(const vsbpp_options& o);
+vsbpp_options resolve_options(const vsbpp_options* opt);
+}  // namespace vsbpp
+
+namespace {
 
 int32_t check_instance(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                        int32_t heuristic, const vsbpp_options& o, bool check_order) {
@@ -58,80 +69,208 @@ vsbpp_options resolve(const vsbpp_options* opt) {
   return o;
 }
 
-struct DeviceState {
-  bool probed = false;
-  bool ok = false;
-  int max_lds_block = 65536;
-};
-
 std::mutex g_mu;
-DeviceState g_dev;
 
-bool device_ok_locked() {
-  if (!g_dev.probed) {
-    g_dev.probed = true;
+int round_up(int x, int to) { return ((x + to - 1) / to) * to; }
+
+}  // namespace
+
+namespace vsbpp {
+
+const DevInfo& device_info() {
+  static DevInfo info;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!info.probed) {
+    info.probed = true;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
       (void)hipGetLastError();
-      return false;
+      return info;
     }
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
     hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
-    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return false;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return info;
+    }
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return info;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
             hipSuccess &&
         lds > 0)
-      g_dev.max_lds_block = lds;
-    g_dev.ok = true;
+      info.max_lds_block = lds;
+    info.cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 1;
+    info.ok = true;
   }
-  return g_dev.ok;
+  return info;
 }
 
-int round_up(int x, int to) { return ((x + to - 1) / to) * to; }
+namespace {
 
-// Plans and launches one batch.  All pointers in `a` are device pointers.
-int32_t launch_batch(BatchArgs a, int32_t heuristic, int32_t max_types, hipStream_t s) {
-  const bool wide = a.max_cap > 0x7FFF || a.max_items > 0xFFFF;
-  hipError_t e = hipSuccess;
+bool is_wide(const BatchArgs& a) { return a.max_cap > 0x7FFF || a.max_items > 0xFFFF; }
+
+struct PlainShape {
+  int slots;
+  size_t per_wave;
+  int max_wpb;
+};
+
+int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
+  const bool wide = is_wide(a);
+  sh->slots = round_up(a.max_items, 256);
+  if (!wide && sh->slots > 65536) return VSBPP_E_SIZE;
+  sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide);
+  sh->max_wpb = (int)((size_t)device_info().max_lds_block / sh->per_wave);
+  if (sh->max_wpb < 1) return VSBPP_E_SIZE;
+  if (sh->max_wpb > 4) sh->max_wpb = 4;
+  return VSBPP_OK;
+}
+
+int h_nbslots(int heuristic, const BatchArgs& a) {
+  return round_up(a.max_types + 2 * (heuristic == VSBPP_H1 ? a.s1 : a.s2), 4);
+}
+
+size_t h_lds(int heuristic, const BatchArgs& a, int block) {
+  const bool wide = is_wide(a);
+  const int nbs = h_nbslots(heuristic, a);
+  return heuristic == VSBPP_H1 ? h1_lds_bytes(nbs, a.s1, block, wide)
+                               : h2_lds_bytes(nbs, block, h2_group(a.s2), wide);
+}
+
+// largest workgroup of the given granularity that fits the LDS budget
+int h_fit_block(int heuristic, const BatchArgs& a, int want) {
+  const int gran = heuristic == VSBPP_H2 ? h2_group(a.s2) : 64;
+  int b = want < gran ? gran : (want / gran) * gran;
+  if (b > 1024) b = (1024 / gran) * gran;
+  const size_t budget = (size_t)(device_info().max_lds_block - kStaticLdsReserve);
+  while (b > gran && h_lds(heuristic, a, b) > budget) b -= gran;
+  if (h_lds(heuristic, a, b) > budget) return 0;
+  return b;
+}
+
+}  // namespace
+
+int32_t check_cfg(const LaunchCfg& c, int heuristic, const BatchArgs& a) {
+  if (c.mode < 0 || c.mode > 1 || c.lpt < 0 || c.lpt > 1) return VSBPP_E_OPTION;
+  if (c.lpt && a.num > kLptMax) return VSBPP_E_OPTION;
   if (heuristic <= VSBPP_WF) {
-    const int slots = round_up(a.max_items, 256);
-    if (!wide && slots > 65536) return VSBPP_E_SIZE;
-    a.slots = slots;
-    const size_t per_wave = vsbpp::plain_lds_per_wave(slots, a.max_items, wide);
-    int wpb = (int)((size_t)g_dev.max_lds_block / per_wave);
-    if (wpb < 1) return VSBPP_E_SIZE;
-    if (wpb > 4) wpb = 4;
-    e = vsbpp::launch_plain(a, heuristic, wide, wpb, per_wave, s);
-  } else if (heuristic == VSBPP_H1) {
-    const int nbslots = round_up(max_types + 2 * a.s1, 4);
-    const int packers = (a.max_items + a.s1 - 1) / a.s1;
-    int block = round_up(packers, 64);
-    if (block > 256) block = 256;
-    while (block > 64 &&
-           vsbpp::h1_lds_bytes(nbslots, a.s1, block, wide) > (size_t)g_dev.max_lds_block)
-      block -= 64;
-    if (vsbpp::h1_lds_bytes(nbslots, a.s1, block, wide) > (size_t)g_dev.max_lds_block)
-      return VSBPP_E_SIZE;
-    e = vsbpp::launch_h1(a, wide, nbslots, block, s);
+    if (c.wpb < 1 || c.wpb > 4) return VSBPP_E_OPTION;
   } else {
-    const int nbslots = round_up(max_types + 2 * a.s2, 4);
-    const int group = vsbpp::h2_group(a.s2);
-    int block = group >= 256 ? group : 256;
-    while (block > group &&
-           vsbpp::h2_lds_bytes(nbslots, block, group, wide) > (size_t)g_dev.max_lds_block)
-      block -= group;
-    if (vsbpp::h2_lds_bytes(nbslots, block, group, wide) > (size_t)g_dev.max_lds_block)
-      return VSBPP_E_SIZE;
-    e = vsbpp::launch_h2(a, wide, nbslots, block, s);
-  }
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return VSBPP_E_DEVICE;
+    if (c.block < 64 || c.block > 1024 || (c.block & 63)) return VSBPP_E_OPTION;
+    if (heuristic == VSBPP_H2 && (c.block % h2_group(a.s2))) return VSBPP_E_OPTION;
   }
   return VSBPP_OK;
+}
+
+LaunchCfg default_cfg(int heuristic, const BatchArgs& a) {
+  LaunchCfg c;
+  if (heuristic == VSBPP_H1) {
+    const int packers = (a.max_items + a.s1 - 1) / a.s1;
+    int b = round_up(packers, 64);
+    c.block = b > 256 ? 256 : b;
+  } else if (heuristic == VSBPP_H2) {
+    const int g = h2_group(a.s2);
+    c.block = g >= 256 ? g : 256;
+  }
+  return c;
+}
+
+std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a) {
+  std::vector<LaunchCfg> v;
+  const bool lpt_ok = a.num <= kLptMax;
+  for (int mode = 0; mode <= 1; ++mode) {
+    for (int lpt = 0; lpt <= (lpt_ok ? 1 : 0); ++lpt) {
+      if (heuristic <= VSBPP_WF) {
+        for (int wpb : {1, 2, 4}) {
+          LaunchCfg c;
+          c.mode = mode;
+          c.lpt = lpt;
+          c.wpb = wpb;
+          v.push_back(c);
+        }
+      } else {
+        const int gran = heuristic == VSBPP_H2 ? h2_group(a.s2) : 64;
+        for (int b = gran; b <= 1024; b *= 2) {
+          if (b % gran) continue;
+          LaunchCfg c;
+          c.mode = mode;
+          c.lpt = lpt;
+          c.block = b;
+          v.push_back(c);
+        }
+      }
+    }
+  }
+  return v;
+}
+
+thread_local char g_last_error[256] = "";
+
+void set_last_error(const char* where, hipError_t e) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e),
+                (int)e);
+}
+
+int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* queue,
+                      int32_t* sched, hipStream_t s) {
+  if (a.num <= 0) return VSBPP_OK;
+  const DevInfo& d = device_info();
+  const bool wide = is_wide(a);
+  hipError_t e = hipSuccess;
+  a.queue = nullptr;
+  a.sched = nullptr;
+  if ((c.mode == 1 && !queue) || (c.lpt && !sched)) return VSBPP_E_OPTION;
+  if (c.lpt) {
+    e = launch_lpt_schedule(a.item_off, a.num, sched, s);
+    if (e != hipSuccess) goto fail;
+    a.sched = sched;
+  }
+  if (c.mode == 1) {
+    e = launch_queue_reset(queue, s);
+    if (e != hipSuccess) goto fail;
+    a.queue = queue;
+  }
+  if (heuristic <= VSBPP_WF) {
+    PlainShape sh;
+    int32_t rc = plain_shape(a, &sh);
+    if (rc != VSBPP_OK) return rc;
+    a.slots = sh.slots;
+    const int wpb = c.wpb < sh.max_wpb ? c.wpb : sh.max_wpb;
+    int grid = 0;
+    if (c.mode == 1) grid = d.cus * plain_blocks_per_cu(heuristic, wide, wpb, sh.per_wave);
+    e = launch_plain_grid(a, heuristic, wide, wpb, sh.per_wave, grid, s);
+  } else {
+    const int block = h_fit_block(heuristic, a, c.block);
+    if (block == 0) return VSBPP_E_SIZE;
+    const int nbs = h_nbslots(heuristic, a);
+    int grid = 0;
+    if (c.mode == 1) {
+      const size_t lds = h_lds(heuristic, a, block);
+      grid = d.cus * (heuristic == VSBPP_H1 ? h1_blocks_per_cu(wide, block, lds)
+                                            : h2_blocks_per_cu(wide, block, lds));
+    }
+    e = heuristic == VSBPP_H1 ? launch_h1_grid(a, wide, nbs, block, grid, s)
+                              : launch_h2_grid(a, wide, nbs, block, grid, s);
+  }
+  if (e == hipSuccess) return VSBPP_OK;
+fail:
+  set_last_error(heuristic <= VSBPP_WF ? "plain launch" : heuristic == VSBPP_H1 ? "H1 launch"
+                                                                               : "H2 launch",
+                 e);
+  (void)hipGetLastError();
+  return VSBPP_E_DEVICE;
+}
+
+}  // namespace vsbpp
+
+namespace {
+
+bool device_ok_locked() { return vsbpp::device_info().ok; }
+
+int32_t launch_batch(BatchArgs a, int32_t heuristic, hipStream_t s) {
+  return vsbpp::enqueue_batch(a, heuristic, vsbpp::default_cfg(heuristic, a), nullptr, nullptr,
+                              s);
 }
 
 template <typename T>
@@ -173,6 +312,8 @@ const char* vsbpp_strerror(int32_t code) {
     default: return code >= 0 ? "ok" : "unknown error";
   }
 }
+
+const char* vsbpp_last_error(void) { return vsbpp::g_last_error; }
 
 int32_t vsbpp_device_ok(void) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -232,7 +373,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   a.force_crit = o.force_criterion;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
-  rc = launch_batch(a, heuristic, n, s);
+  rc = launch_batch(a, heuristic, s);
   if (rc != VSBPP_OK) return rc;
   if (hipStreamSynchronize(s) != hipSuccess) return VSBPP_E_DEVICE;
   int32_t nb = 0;
@@ -301,7 +442,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
   a.force_crit = o.force_criterion;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
-  return launch_batch(a, heuristic, max_types, (hipStream_t)hip_stream);
+  return launch_batch(a, heuristic, (hipStream_t)hip_stream);
 }
 
 int32_t vsbpp_best_of(const int64_t* d_cost, int32_t num, int64_t* d_out, void* hip_stream) {
@@ -317,3 +458,8 @@ int32_t vsbpp_best_of(const int64_t* d_cost, int32_t num, int64_t* d_out, void* 
 }
 
 }  // extern "C"
+
+namespace vsbpp {
+int32_t check_options_public(const vsbpp_options& o) { return check_options(o); }
+vsbpp_options resolve_options(const vsbpp_options* opt) { return resolve(opt); }
+}  // namespace vsbpp

@@ -96,3 +96,29 @@ def test_no_device_reports_device_error(V):
     with pytest.raises(V.VsbppError) as e:
         V.pack(np.array([1, 2, 3]), [10, 5], "FF")
     assert e.value.code == -7
+
+
+def test_plan_host_checks(V):
+    L = V._plan_lib()
+    out = ctypes.c_void_p()
+    o = V.options()
+    assert L.vsbpp_plan_create(None, 0, ctypes.byref(o), None, 0, ctypes.byref(out)) == -1
+    d = V._BatchDesc()
+    d.num_instances = 0
+    assert L.vsbpp_plan_create(ctypes.byref(d), 0, ctypes.byref(o), None, 0,
+                               ctypes.byref(out)) == -2
+    d.num_instances = 2
+    assert L.vsbpp_plan_create(ctypes.byref(d), 0, ctypes.byref(o), None, 0,
+                               ctypes.byref(out)) == -1
+    for f in ("weights", "item_off", "capacities", "cap_off", "assignment", "bin_types",
+              "nbins", "cost"):
+        setattr(d, f, 16)
+    d.max_items, d.max_types, d.max_capacity = 10, 3, 100
+    assert L.vsbpp_plan_create(ctypes.byref(d), 7, ctypes.byref(o), None, 0,
+                               ctypes.byref(out)) == -5
+    if not V.device_ok():
+        assert L.vsbpp_plan_create(ctypes.byref(d), 0, ctypes.byref(o), None, 0,
+                                   ctypes.byref(out)) == -7
+        assert out.value is None
+    assert L.vsbpp_plan_run(None, None) == -1
+    L.vsbpp_plan_destroy(None)
