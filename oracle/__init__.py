@@ -23,7 +23,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 FF, BF, WF, H1, H2 = 0, 1, 2, 3, 4
 HEURISTICS = {"FF": FF, "BF": BF, "WF": WF, "H1": H1, "H2": H2}
-TYPE_SMALLEST_FIT, TYPE_LARGEST = 0, 1
+TYPE_SMALLEST_FIT, TYPE_LARGEST, TYPE_LEARNED = 0, 1, 2
+NFEAT, HIDDEN, MAX_OUT = 16, 64, 16
 
 
 def build(force: bool = False) -> str:
@@ -34,10 +35,34 @@ def build(force: bool = False) -> str:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-             "-o", tmp, _SRC]
+             "-o", tmp, _SRC, "-lm"]
         )
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+class Model(ctypes.Structure):
+    """The scorer: bf16 weights as raw uint16, fp32 biases, row-major [out][in]."""
+    _fields_ = [
+        ("n_out", ctypes.c_int32),
+        ("w1", ctypes.c_uint16 * (HIDDEN * NFEAT)),
+        ("b1", ctypes.c_float * HIDDEN),
+        ("w2", ctypes.c_uint16 * (HIDDEN * HIDDEN)),
+        ("b2", ctypes.c_float * HIDDEN),
+        ("w3", ctypes.c_uint16 * (MAX_OUT * HIDDEN)),
+        ("b3", ctypes.c_float * MAX_OUT),
+    ]
+
+
+class Decision(ctypes.Structure):
+    _fields_ = [
+        ("position", ctypes.c_int32),
+        ("weight", ctypes.c_int32),
+        ("plain_type", ctypes.c_int32),
+        ("chosen", ctypes.c_int32),
+        ("feasible", ctypes.c_uint32),
+        ("feat", ctypes.c_float * NFEAT),
+    ]
 
 
 class _Opts(ctypes.Structure):
@@ -48,6 +73,13 @@ class _Opts(ctypes.Structure):
         ("type_rule", ctypes.c_int32),
         ("force_crit", ctypes.c_int32),
         ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("model", ctypes.POINTER(Model)),
+        ("force_event", ctypes.c_int32),
+        ("force_t1", ctypes.c_int32),
+        ("force_t2", ctypes.c_int32),
+        ("trace", ctypes.POINTER(Decision)),
+        ("trace_cap", ctypes.c_int32),
+        ("trace_count", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -93,6 +125,12 @@ def lib():
             f = getattr(L, name)
             f.restype = ctypes.c_int64
             f.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32]
+        L.orc_mlp_forward.restype = None
+        L.orc_mlp_forward.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_float)]
+        L.orc_rollout_label.restype = ctypes.c_int32
+        L.orc_rollout_label.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, i64p]
         L.orc_lb_sum.restype = ctypes.c_int64
         L.orc_lb_sum.argtypes = [i32p, ctypes.c_int32]
         _lib = L
@@ -142,7 +180,8 @@ def perm(seed: int, m: int) -> np.ndarray:
 
 def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
          type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
-         order=None) -> Packing:
+         order=None, model: "Model | None" = None, force_event: int = -1,
+         force_types=(0, 0), trace: bool = False) -> Packing:
     w = _i32(weights)
     c = _i32(caps)
     m = int(w.size)
@@ -151,6 +190,17 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     cost = ctypes.c_int64(0)
     st = _Stats()
     o = _Opts(seed & (2**64 - 1), s1, s2, type_rule, force_crit, None)
+    if model is not None:
+        o.model = ctypes.pointer(model)
+    o.force_event = force_event
+    o.force_t1, o.force_t2 = int(force_types[0]), int(force_types[1])
+    tr_arr = None
+    tr_count = ctypes.c_int32(0)
+    if trace:
+        tr_arr = (Decision * max(m, 1))()
+        o.trace = tr_arr
+        o.trace_cap = m
+        o.trace_count = ctypes.pointer(tr_count)
     order_arr = None
     if order is not None:
         order_arr = _i32(order)
@@ -162,6 +212,8 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     if rc < 0:
         raise OracleError(rc)
     stats = {f: int(getattr(st, f)) for f, _ in _Stats._fields_}
+    if trace:
+        stats["decisions"] = [tr_arr[i] for i in range(tr_count.value)]
     return Packing(assign[:m].copy(), types[:rc].copy(), int(rc), int(cost.value), stats)
 
 
@@ -211,3 +263,49 @@ def opt_partitions(weights, caps) -> int:
 def opt_subset_dp(weights, caps) -> int:
     w, c = _i32(weights), _i32(caps)
     return int(lib().orc_opt_subset_dp(_p32(w), int(w.size), _p32(c), int(c.size)))
+
+
+def bf16_bits(x) -> np.ndarray:
+    """fp32 -> bfloat16 bit patterns, round to nearest even (test helper)."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    r = (a + 0x7FFF + ((a >> 16) & 1)) >> 16
+    return r.astype(np.uint16)
+
+
+def bf16_to_f32(bits) -> np.ndarray:
+    return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32)
+
+
+def make_model(w1, b1, w2, b2, w3, b3) -> Model:
+    """Model from fp32 arrays (weights rounded to bf16)."""
+    mdl = Model()
+    n_out = int(np.asarray(b3).size)
+    mdl.n_out = n_out
+    mdl.w1[:] = bf16_bits(np.asarray(w1).reshape(-1)).tolist()
+    mdl.b1[:] = np.asarray(b1, dtype=np.float32).tolist()
+    mdl.w2[:] = bf16_bits(np.asarray(w2).reshape(-1)).tolist()
+    mdl.b2[:] = np.asarray(b2, dtype=np.float32).tolist()
+    w3b = np.zeros(MAX_OUT * HIDDEN, dtype=np.uint16)
+    w3b[:n_out * HIDDEN] = bf16_bits(np.asarray(w3).reshape(-1))
+    mdl.w3[:] = w3b.tolist()
+    b3f = np.zeros(MAX_OUT, dtype=np.float32)
+    b3f[:n_out] = np.asarray(b3, dtype=np.float32)
+    mdl.b3[:] = b3f.tolist()
+    return mdl
+
+
+def mlp_forward(model: Model, x) -> np.ndarray:
+    xv = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    z = np.zeros(MAX_OUT, dtype=np.float32)
+    lib().orc_mlp_forward(ctypes.byref(model), xv.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                          z.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    return z[:model.n_out].copy()
+
+
+def rollout_label(weights, caps, crit: int, d: int):
+    """(label, values) of decision d of a plain run (depth-2 lookahead)."""
+    w, c = _i32(weights), _i32(caps)
+    vals = np.zeros(c.size, dtype=np.int64)
+    lab = lib().orc_rollout_label(_p32(w), int(w.size), _p32(c), int(c.size), crit, d,
+                                  vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return int(lab), vals

@@ -10,6 +10,7 @@
 #include "vsbpp_oracle.h"
 
 #include <stdlib.h>
+#include <math.h>
 #include <string.h>
 
 /* ---------------------------------------------------------------------- */
@@ -121,9 +122,11 @@ static int32_t open_type(const int32_t* caps, int32_t n, int32_t w, int32_t rule
  * has not divided yet divides once, adding an empty bin of its type.
  * `suffix_min` is the smallest weight among this item and all later items of
  * the same packer; it only feeds the work counters. */
+typedef int32_t (*type_chooser)(void* ctx, int32_t w);
+
 static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
                      int32_t crit, int32_t rule5, int32_t type_rule,
-                     int64_t suffix_min, orc_stats* st) {
+                     int64_t suffix_min, orc_stats* st, type_chooser choose, void* cctx) {
   int32_t best = -1;
   int64_t best_after = 0;
   for (int32_t b = 0; b < p->nb; ++b) {
@@ -144,7 +147,7 @@ static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
     }
   }
   if (best < 0) {
-    pk_push(p, open_type(caps, n, w, type_rule));
+    pk_push(p, choose ? choose(cctx, w) : open_type(caps, n, w, type_rule));
     best = p->nb - 1;
     if (st) st->new_bins++;
   }
@@ -207,7 +210,12 @@ static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_
   if (heuristic < ORC_FF || heuristic > ORC_H2) return ORC_E_HEURISTIC;
   if (o) {
     if (o->s1 < 1 || o->s2 < 1 || o->s2 > 6) return ORC_E_OPTION;
-    if (o->type_rule != ORC_TYPE_SMALLEST_FIT && o->type_rule != ORC_TYPE_LARGEST)
+    if (o->type_rule != ORC_TYPE_SMALLEST_FIT && o->type_rule != ORC_TYPE_LARGEST &&
+        o->type_rule != ORC_TYPE_LEARNED)
+      return ORC_E_OPTION;
+    if (o->type_rule == ORC_TYPE_LEARNED &&
+        (!o->model || o->model->n_out < 1 || o->model->n_out > ORC_MAX_OUT ||
+         heuristic > ORC_WF))
       return ORC_E_OPTION;
     if (o->force_crit < -1 || o->force_crit > ORC_WF) return ORC_E_OPTION;
     if (o->order) {
@@ -234,8 +242,130 @@ static int32_t item_at(const orc_opts* o, int32_t m, int32_t q, int32_t heuristi
   return q; /* plain heuristics: input order */
 }
 
+/* ---------------------------------------------------------------------- */
+/* Learned bin-type scorer (decision = an item that fits no open bin).     */
+/* ---------------------------------------------------------------------- */
+
+static float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, sizeof f);
+  return f;
+}
+
+static float relu(float v) { return v > 0.0f ? v : 0.0f; }
+
+/* Every output is its bias followed by a chain of fused multiply-adds over
+ * the inputs in index order, in fp32; hidden layers take ReLU. */
+void orc_mlp_forward(const orc_model* mdl, const float* x, float* z) {
+  float h1[ORC_HIDDEN], h2[ORC_HIDDEN];
+  for (int l = 0; l < ORC_HIDDEN; ++l) {
+    float acc = mdl->b1[l];
+    for (int i = 0; i < ORC_NFEAT; ++i) acc = fmaf(bf16_to_f32(mdl->w1[l * ORC_NFEAT + i]), x[i], acc);
+    h1[l] = relu(acc);
+  }
+  for (int l = 0; l < ORC_HIDDEN; ++l) {
+    float acc = mdl->b2[l];
+    for (int j = 0; j < ORC_HIDDEN; ++j) acc = fmaf(bf16_to_f32(mdl->w2[l * ORC_HIDDEN + j]), h1[j], acc);
+    h2[l] = relu(acc);
+  }
+  for (int k = 0; k < mdl->n_out; ++k) {
+    float acc = mdl->b3[k];
+    for (int j = 0; j < ORC_HIDDEN; ++j) acc = fmaf(bf16_to_f32(mdl->w3[k * ORC_HIDDEN + j]), h2[j], acc);
+    z[k] = acc;
+  }
+}
+
+/* state of a plain run that the decision features read */
+typedef struct {
+  const int32_t* caps;
+  int32_t n, m, q, w;
+  int64_t total, placed;     /* weight of all items; of positions < q        */
+  int64_t smin_after;        /* smallest weight at positions > q, or -1      */
+  int32_t nb;                /* bins opened so far                           */
+  int32_t hist[6];           /* bins by room bucket                          */
+  int32_t event;             /* decisions so far                             */
+  const orc_opts* o;
+} plain_ctx;
+
+/* room bucket of the histogram: floor(6 r / (B_1 + 1)) in 0..5 */
+static int32_t room_bucket(int64_t r, int32_t b1) {
+  int64_t k = (6 * r) / ((int64_t)b1 + 1);
+  return (int32_t)(k > 5 ? 5 : k);
+}
+
+/* The 16 decision features (fp32):
+ *  0  w / B_1
+ *  1  items after this one / m
+ *  2  mean weight of the items after this one / B_1 (0 if none)
+ *  3  smallest weight after this one / B_1 (1 if none)
+ *  4  bins opened so far / m
+ *  5..10  share of the opened bins in each room bucket floor(6r/(B_1+1))
+ *  11..14 B_2..B_5 / B_1 (0 beyond n)
+ *  15 w / smallest capacity >= w */
+static void decision_features(const plain_ctx* c, float* x) {
+  const float b1 = (float)c->caps[0];
+  const int32_t rem = c->m - c->q - 1;
+  const int64_t rsum = c->total - c->placed - c->w;
+  x[0] = (float)c->w / b1;
+  x[1] = (float)rem / (float)c->m;
+  x[2] = rem > 0 ? (float)rsum / (float)((int64_t)rem * (int64_t)c->caps[0]) : 0.0f;
+  x[3] = rem > 0 ? (float)c->smin_after / b1 : 1.0f;
+  x[4] = (float)c->nb / (float)c->m;
+  const float den = (float)(c->nb > 0 ? c->nb : 1);
+  for (int k = 0; k < 6; ++k) x[5 + k] = (float)c->hist[k] / den;
+  for (int k = 1; k <= 4; ++k) x[10 + k] = k < c->n ? (float)c->caps[k] / b1 : 0.0f;
+  x[15] = (float)c->w / (float)c->caps[open_type(c->caps, c->n, c->w, ORC_TYPE_SMALLEST_FIT)];
+}
+
+static int32_t plain_choose(void* vc, int32_t w) {
+  plain_ctx* c = (plain_ctx*)vc;
+  const orc_opts* o = c->o;
+  const int32_t base_rule = o->type_rule == ORC_TYPE_LEARNED ? ORC_TYPE_SMALLEST_FIT : o->type_rule;
+  const int32_t base = open_type(c->caps, c->n, w, base_rule);
+  const int32_t d = c->event++;
+  uint32_t feasible = 0;
+  for (int32_t k = 0; k < c->n; ++k)
+    if (c->caps[k] >= w) feasible |= 1u << k;
+  int32_t chosen = base;
+  float x[ORC_NFEAT];
+  const int need_feat = (o->type_rule == ORC_TYPE_LEARNED) || (o->trace && d < o->trace_cap);
+  if (need_feat) decision_features(c, x);
+  if (o->type_rule == ORC_TYPE_LEARNED) {
+    float z[ORC_MAX_OUT];
+    orc_mlp_forward(o->model, x, z);
+    const int32_t kmax = c->n < o->model->n_out ? c->n : o->model->n_out;
+    int32_t best = 0; /* type 0 always holds the item */
+    int finite = 1;
+    for (int32_t k = 0; k < kmax; ++k) finite &= isfinite(z[k]) ? 1 : 0;
+    for (int32_t k = 1; k < kmax; ++k)
+      if ((feasible >> k) & 1u)
+        if (z[k] > z[best]) best = k;
+    /* the scorer only proposes: a non-finite output falls back to the base rule */
+    chosen = finite ? best : base;
+  }
+  if (o->force_event >= 0) {
+    int32_t t = -1;
+    if (d == o->force_event) t = o->force_t1;
+    else if (d == o->force_event + 1) t = o->force_t2;
+    if (t >= 0 && t < c->n && ((feasible >> t) & 1u)) chosen = t;
+  }
+  if (o->trace && d < o->trace_cap) {
+    orc_decision* r = &o->trace[d];
+    r->position = c->q;
+    r->weight = w;
+    r->plain_type = base;
+    r->chosen = chosen;
+    r->feasible = feasible;
+    memcpy(r->feat, x, sizeof x);
+  }
+  return chosen;
+}
+
 /* Plain FF/BF/WF (Section 1): one packer over the whole list, starting with
- * no bins, one fixed criterion, no Rule 2 and no Rule 5. */
+ * no bins, one fixed criterion, no Rule 2 and no Rule 5.  The type of a bin
+ * opened when nothing fits follows the type rule, the scorer, or a forced
+ * choice at one decision and the next. */
 static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                          int32_t crit, const orc_opts* o, int32_t* assign,
                          int32_t* types, int64_t* cost, orc_stats* st) {
@@ -247,10 +377,30 @@ static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32
     int64_t v = w[items[q]];
     smin[q] = (q == m - 1 || v < smin[q + 1]) ? v : smin[q + 1];
   }
+  plain_ctx c;
+  memset(&c, 0, sizeof c);
+  c.caps = caps;
+  c.n = n;
+  c.m = m;
+  c.o = o;
+  for (int32_t q = 0; q < m; ++q) c.total += w[items[q]];
   opacker p;
   pk_init(&p);
-  for (int32_t q = 0; q < m; ++q)
-    local[q] = place(&p, caps, n, w[items[q]], crit, 0, o->type_rule, smin[q], st);
+  for (int32_t q = 0; q < m; ++q) {
+    const int32_t wq = w[items[q]];
+    c.q = q;
+    c.w = wq;
+    c.smin_after = q + 1 < m ? smin[q + 1] : -1;
+    c.nb = p.nb;
+    const int32_t nb_before = p.nb;
+    const int32_t b = place(&p, caps, n, wq, crit, 0, o->type_rule, smin[q], st, plain_choose, &c);
+    local[q] = b;
+    const int64_t room = (int64_t)caps[p.b[b].type] - p.b[b].load;
+    if (b != nb_before) c.hist[room_bucket(room + wq, caps[0])]--;
+    c.hist[room_bucket(room, caps[0])]++;
+    c.placed += wq;
+  }
+  if (o->trace_count) *o->trace_count = c.event;
   *cost = 0;
   int32_t nb = emit_packer(&p, caps, items, local, m, 0, assign, types, cost);
   if (st) st->packers += 1;
@@ -259,6 +409,49 @@ static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32
   free(local);
   free(smin);
   return nb;
+}
+
+int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                          int32_t crit, int32_t d, int64_t* values) {
+  if (!w || !caps || !values) return ORC_E_NULL;
+  if (crit < ORC_FF || crit > ORC_WF || d < 0) return ORC_E_OPTION;
+  int32_t* assign = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int32_t* types = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
+  int32_t count = 0;
+  int64_t cost = 0;
+  orc_opts o = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count};
+  int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
+  int32_t label = -1;
+  if (rc >= 0 && d < count) {
+    const uint32_t feasible = tr[d].feasible;
+    const int32_t base = tr[d].plain_type;
+    int64_t best = -1;
+    for (int32_t k1 = 0; k1 < n; ++k1) {
+      values[k1] = -1;
+      if (!((feasible >> k1) & 1u)) continue;
+      int64_t v = -1;
+      for (int32_t k2 = 0; k2 < n; ++k2) {
+        orc_opts f = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL};
+        orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
+        if (v < 0 || cost < v) v = cost;
+      }
+      values[k1] = v;
+      if (best < 0 || v < best) best = v;
+    }
+    if (values[base] == best) label = base;
+    else
+      for (int32_t k1 = 0; k1 < n && label < 0; ++k1)
+        if (values[k1] == best) label = k1;
+  } else if (rc >= 0) {
+    label = ORC_E_OPTION; /* the run has fewer than d+1 decisions */
+  } else {
+    label = rc;
+  }
+  free(assign);
+  free(types);
+  free(tr);
+  return label;
 }
 
 /* First heuristic (Section 6.3).  Sublist I holds positions
@@ -291,7 +484,7 @@ static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
     for (int32_t t = 0; t < k; ++t) {
       int32_t c = o->force_crit >= 0 ? o->force_crit
                                      : orc_criterion(ck, (uint64_t)(q0 + t));
-      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, smin[t], st);
+      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, smin[t], st, NULL, NULL);
     }
     base += emit_packer(&p, caps, items, local, k, base, assign, types, cost);
     pk_free(&p);
@@ -361,7 +554,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
         int32_t c = o->force_crit >= 0
                         ? o->force_crit
                         : orc_criterion(ck, (uint64_t)(((int64_t)I * P + r) * S + t));
-        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, smin[t], st);
+        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, smin[t], st, NULL, NULL);
       }
       int64_t c = packer_cost(&p, caps);
       if (best_r < 0 || c < best_cost) {
@@ -381,7 +574,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
                       ? o->force_crit
                       : orc_criterion(ck, (uint64_t)(((int64_t)I * P + best_r) * S + t));
       placed_items[t] = items[order[t]];
-      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, NULL);
+      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, NULL, NULL, NULL);
     }
     base += emit_packer(&p, caps, placed_items, local, k, base, assign, types, cost);
     pk_free(&p);
@@ -393,7 +586,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
 int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                  int32_t heuristic, const orc_opts* opt, int32_t* assign,
                  int32_t* types, int64_t* cost, orc_stats* stats) {
-  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL};
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL};
   const orc_opts* o = opt ? opt : &def;
   if (!assign || !types || !cost) return ORC_E_NULL;
   int32_t rc = validate(w, m, caps, n, heuristic, o);
@@ -428,7 +621,7 @@ int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
     for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
   for (int32_t t = 0; t < m; ++t) {
     items[t] = t;
-    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, NULL);
+    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, NULL, NULL, NULL);
   }
   *cost = 0;
   int32_t nb = emit_packer(&p, caps, items, local, m, 0, assign, types, cost);

@@ -26,7 +26,32 @@ extern "C" {
  * P-system heuristics (Sections 6.3 and 6.4) */
 enum { ORC_FF = 0, ORC_BF = 1, ORC_WF = 2, ORC_H1 = 3, ORC_H2 = 4 };
 /* rule for the type of a newly opened bin when no open bin fits */
-enum { ORC_TYPE_SMALLEST_FIT = 0, ORC_TYPE_LARGEST = 1 };
+enum { ORC_TYPE_SMALLEST_FIT = 0, ORC_TYPE_LARGEST = 1, ORC_TYPE_LEARNED = 2 };
+
+/* Learned bin-type scorer: MLP 16 -> 64 -> 64 -> n_out with ReLU, weights in
+ * bfloat16 (raw 16-bit patterns), biases in fp32, row-major [out][in]. */
+#define ORC_NFEAT 16
+#define ORC_HIDDEN 64
+#define ORC_MAX_OUT 16
+typedef struct {
+  int32_t n_out;
+  uint16_t w1[ORC_HIDDEN * ORC_NFEAT];
+  float b1[ORC_HIDDEN];
+  uint16_t w2[ORC_HIDDEN * ORC_HIDDEN];
+  float b2[ORC_HIDDEN];
+  uint16_t w3[ORC_MAX_OUT * ORC_HIDDEN];
+  float b3[ORC_MAX_OUT];
+} orc_model;
+
+/* one decision (an item that fits no open bin) of a plain FF/BF/WF run */
+typedef struct {
+  int32_t position;   /* position of the item in processing order      */
+  int32_t weight;
+  int32_t plain_type; /* type the base rule would open                  */
+  int32_t chosen;     /* type actually opened                           */
+  uint32_t feasible;  /* bit k set when B_k >= weight                   */
+  float feat[ORC_NFEAT];
+} orc_decision;
 enum { ORC_OK = 0, ORC_E_NULL = -1, ORC_E_SIZE = -2, ORC_E_CAPS = -3,
        ORC_E_WEIGHT = -4, ORC_E_HEURISTIC = -5, ORC_E_OPTION = -6 };
 
@@ -37,6 +62,14 @@ typedef struct {
   int32_t type_rule;      /* ORC_TYPE_*                                    */
   int32_t force_crit;     /* -1: drawn per placement; else ORC_FF/BF/WF    */
   const int32_t* order;   /* optional: order[q] = item at position q       */
+  const orc_model* model; /* ORC_TYPE_LEARNED: the scorer                  */
+  int32_t force_event;    /* plain heuristics: decision number d whose type
+                             is forced (-1: none)                          */
+  int32_t force_t1;       /* type forced at decision d                     */
+  int32_t force_t2;       /* type forced at decision d + 1                 */
+  orc_decision* trace;    /* optional: receives the run's decisions        */
+  int32_t trace_cap;      /* capacity of trace                             */
+  int32_t* trace_count;   /* number of decisions of the run                */
 } orc_opts;
 
 typedef struct {
@@ -74,6 +107,19 @@ int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
                         int32_t n, const int32_t* crit, int32_t rule2,
                         int32_t rule5, int32_t type_rule, int32_t* assign,
                         int32_t* types, int64_t* cost);
+
+/* Scorer forward pass: z[0..n_out) from x[16] (fp32, fused multiply-add
+ * chains in index order). */
+void orc_mlp_forward(const orc_model* mdl, const float* x, float* z);
+
+/* Depth-2 lookahead label of decision d of a plain run with criterion crit:
+ * for every feasible type k1 at d, V(k1) = min over k2 of the cost of the
+ * run with k1 forced at d and k2 at d+1 (the base rule elsewhere); the label
+ * is argmin V, ties to the base rule's own choice, else the lowest type.
+ * values[n] receives V (-1 for infeasible types).  Returns the label or a
+ * negative code. */
+int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                          int32_t crit, int32_t d, int64_t* values);
 
 /* lower bounds on the optimum */
 int64_t orc_lb_sum(const int32_t* w, int32_t m);

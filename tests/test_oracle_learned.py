@@ -1,0 +1,190 @@
+"""Pins of the oracle's learned bin-type scorer: the MLP forward pass, the
+decision features, forced decisions and depth-2 lookahead labels.  CPU only."""
+import numpy as np
+import pytest
+
+from paper_1602_08735_amd import inputs
+
+
+def random_model(orc, rng, n_out=5, scale=0.3):
+    return orc.make_model(rng.normal(0, scale, (64, 16)), rng.normal(0, 0.1, 64),
+                          rng.normal(0, scale / 2, (64, 64)), rng.normal(0, 0.1, 64),
+                          rng.normal(0, scale, (n_out, 64)), rng.normal(0, 0.1, n_out))
+
+
+def f64_forward(orc, mdl, x):
+    """The same network in float64 from the bf16 weights (independent code)."""
+    w1 = orc.bf16_to_f32(np.array(mdl.w1)).astype(np.float64).reshape(64, 16)
+    w2 = orc.bf16_to_f32(np.array(mdl.w2)).astype(np.float64).reshape(64, 64)
+    w3 = orc.bf16_to_f32(np.array(mdl.w3)).astype(np.float64).reshape(16, 64)[:mdl.n_out]
+    b1, b2 = np.array(mdl.b1, np.float64), np.array(mdl.b2, np.float64)
+    b3 = np.array(mdl.b3, np.float64)[:mdl.n_out]
+    h1 = np.maximum(w1 @ np.asarray(x, np.float64) + b1, 0)
+    h2 = np.maximum(w2 @ h1 + b2, 0)
+    return w3 @ h2 + b3
+
+
+def test_mlp_forward_matches_float64(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        mdl = random_model(orc, rng)
+        x = rng.uniform(0, 1, 16).astype(np.float32)
+        z = orc.mlp_forward(mdl, x)
+        ref = f64_forward(orc, mdl, x)
+        # fp32 chains of <= 64 fused multiply-adds per layer
+        assert np.allclose(z, ref, rtol=1e-4, atol=1e-4), (z, ref)
+
+
+def test_mlp_exact_construction(orc):
+    """Identity-like weights route relu(x_k) to output k exactly."""
+    w1 = np.zeros((64, 16))
+    w1[:16, :16] = np.eye(16)
+    w2 = np.eye(64)
+    w3 = np.zeros((5, 64))
+    w3[np.arange(5), np.arange(5)] = 1.0
+    mdl = orc.make_model(w1, np.zeros(64), w2, np.zeros(64), w3, np.zeros(5))
+    x = np.array([0.5, -0.25, 0.75, 0.125, 1.5] + [0.0] * 11, dtype=np.float32)
+    z = orc.mlp_forward(mdl, x)
+    assert z.tolist() == [0.5, 0.0, 0.75, 0.125, 1.5]
+
+
+def test_bf16_rounding(orc):
+    v = np.array([1.0, 1.00390625, 1.005859375, -2.5, 3.0e-3], dtype=np.float32)
+    b = orc.bf16_to_f32(orc.bf16_bits(v))
+    assert b[0] == 1.0 and b[1] == 1.0  # halfway rounds to even
+    assert b[2] == np.float32(1.0078125)
+    assert b[3] == -2.5
+    assert abs(b[4] - 3.0e-3) / 3.0e-3 < 2 ** -8
+
+
+def _constant_model(orc, b3):
+    z = np.zeros
+    return orc.make_model(z((64, 16)), z(64), z((64, 64)), z(64), z((len(b3), 64)), b3)
+
+
+@pytest.mark.parametrize("h", ["FF", "BF", "WF"])
+def test_learned_rule_reduces_to_fixed_rules(orc, h):
+    """A scorer whose output favours type 0 opens B_1 bins (the LARGEST rule);
+    one favouring the highest feasible index opens the smallest fitting bin."""
+    rng = np.random.default_rng(2)
+    b = inputs.random_batch(rng, 30, 1, 300)
+    for i in range(b.n_instances):
+        w, caps, _ = b.instance(i)
+        n = caps.size
+        big = _constant_model(orc, [1.0] + [0.0] * (n - 1))
+        ramp = _constant_model(orc, np.arange(n, dtype=np.float64))
+        r_big = orc.pack(w, caps, h, type_rule=orc.TYPE_LEARNED, model=big)
+        r_lg = orc.pack(w, caps, h, type_rule=orc.TYPE_LARGEST)
+        assert np.array_equal(r_big.assignment, r_lg.assignment) and r_big.cost == r_lg.cost
+        r_ramp = orc.pack(w, caps, h, type_rule=orc.TYPE_LEARNED, model=ramp)
+        r_sf = orc.pack(w, caps, h)
+        assert np.array_equal(r_ramp.assignment, r_sf.assignment) and r_ramp.cost == r_sf.cost
+
+
+def test_decision_features_recount(orc):
+    """Features recomputed from the packing itself: the rooms of the bins just
+    before each decision come from the assignment of the earlier items."""
+    rng = np.random.default_rng(3)
+    for h in ("FF", "BF", "WF"):
+        for i in range(6):
+            w, caps = inputs.c2_instance(rng, 300)
+            r = orc.pack(w, caps, h, trace=True)
+            dec = r.stats["decisions"]
+            m, b1 = w.size, int(caps[0])
+            assert len(dec) == r.nbins  # every plain bin is opened at a decision
+            for d, e in enumerate(dec):
+                q = e.position
+                x = np.array(e.feat, dtype=np.float32)
+                assert e.weight == w[q]
+                assert x[0] == np.float32(w[q]) / np.float32(b1)
+                assert x[1] == np.float32(m - q - 1) / np.float32(m)
+                rem = w[q + 1:].astype(np.int64)
+                if rem.size:
+                    assert x[2] == np.float32(rem.sum()) / np.float32(rem.size * b1)
+                    assert x[3] == np.float32(rem.min()) / np.float32(b1)
+                else:
+                    assert x[2] == 0.0 and x[3] == 1.0
+                assert x[4] == np.float32(d) / np.float32(m)
+                load = np.bincount(r.assignment[:q], weights=w[:q], minlength=d)[:d]
+                room = caps[r.bin_types[:d]].astype(np.int64) - load.astype(np.int64)
+                hist = np.bincount(np.minimum(5, 6 * room // (b1 + 1)), minlength=6)
+                den = np.float32(max(d, 1))
+                assert np.array_equal(x[5:11], hist.astype(np.float32) / den)
+                for k in range(1, 5):
+                    exp = np.float32(caps[k]) / np.float32(b1) if k < caps.size else 0.0
+                    assert x[10 + k] == exp
+                sf = max(k for k in range(caps.size) if caps[k] >= w[q])
+                assert x[15] == np.float32(w[q]) / np.float32(caps[sf])
+                assert e.plain_type == sf and e.chosen == sf
+                assert e.feasible == sum(1 << k for k in range(caps.size) if caps[k] >= w[q])
+
+
+def test_forced_decisions(orc):
+    rng = np.random.default_rng(4)
+    w, caps = inputs.c2_instance(rng, 400)
+    plain = orc.pack(w, caps, "BF", trace=True)
+    dec = plain.stats["decisions"]
+    for d in (0, 3, 17, len(dec) - 2):
+        # forcing the plain choices reproduces the plain run
+        same = orc.pack(w, caps, "BF", force_event=d,
+                        force_types=(dec[d].plain_type, dec[d + 1].plain_type))
+        assert np.array_equal(same.assignment, plain.assignment)
+        # forcing B_1 at decision d: bin d (opened there) becomes type 0 and
+        # everything before it is unchanged
+        r = orc.pack(w, caps, "BF", force_event=d, force_types=(0, dec[d + 1].plain_type))
+        assert r.bin_types[d] == 0
+        assert np.array_equal(r.bin_types[:d], plain.bin_types[:d])
+        q = dec[d].position
+        assert np.array_equal(r.assignment[:q + 1], plain.assignment[:q + 1])
+    # an infeasible forced type falls back to the base rule
+    small = int(np.argmin(caps))
+    d = next(i for i, e in enumerate(dec) if not (e.feasible >> small) & 1)
+    r = orc.pack(w, caps, "BF", force_event=d, force_types=(small, dec[d + 1].plain_type))
+    assert np.array_equal(r.assignment, plain.assignment)
+
+
+def test_rollout_label_invariants(orc):
+    rng = np.random.default_rng(5)
+    for crit in (0, 1, 2):
+        for _ in range(4):
+            w, caps = inputs.c2_instance(rng, 120)
+            plain = orc.pack(w, caps, crit, trace=True)
+            dec = plain.stats["decisions"]
+            for d in rng.choice(len(dec) - 1, size=4, replace=False):
+                lab, vals = orc.rollout_label(w, caps, crit, int(d))
+                feas = dec[d].feasible
+                assert (feas >> lab) & 1
+                for k in range(caps.size):
+                    assert (vals[k] >= 0) == bool((feas >> k) & 1)
+                best = vals[vals >= 0].min()
+                assert vals[lab] == best
+                # the base choice with the base choice next reproduces the plain run
+                assert vals[dec[d].plain_type] <= plain.cost
+                if vals[dec[d].plain_type] == best:
+                    assert lab == dec[d].plain_type
+                else:
+                    assert lab == int(np.flatnonzero(vals == best)[0])
+
+
+def test_rollout_values_against_brute_force(orc):
+    """Every rollout value is the cost of a valid packing: at least OPT."""
+    rng = np.random.default_rng(6)
+    for _ in range(60):
+        w, caps = inputs.random_small(rng, m_max=9, n_max=4, b1_max=25)
+        plain = orc.pack(w, caps, "FF", trace=True)
+        nd = len(plain.stats["decisions"])
+        if nd < 1:
+            continue
+        opt = orc.opt_subset_dp(w, caps)
+        for d in range(nd):
+            lab, vals = orc.rollout_label(w, caps, 0, d)
+            assert lab >= 0
+            assert vals[vals >= 0].min() >= opt
+
+
+def test_non_finite_scores_fall_back(orc):
+    rng = np.random.default_rng(7)
+    w, caps = inputs.c2_instance(rng, 200)
+    bad = _constant_model(orc, [1.0, np.inf, 0.0, 0.0, 0.0])
+    r = orc.pack(w, caps, "BF", type_rule=orc.TYPE_LEARNED, model=bad)
+    assert np.array_equal(r.assignment, orc.pack(w, caps, "BF").assignment)
