@@ -62,8 +62,9 @@ extern "C" {
 
 enum { VSBPP_FF = 0, VSBPP_BF = 1, VSBPP_WF = 2, VSBPP_H1 = 3, VSBPP_H2 = 4 };
 
-/* type of a bin opened when no open bin fits */
-enum { VSBPP_TYPE_SMALLEST_FIT = 0, VSBPP_TYPE_LARGEST = 1 };
+/* type of a bin opened when no open bin fits; LEARNED asks the scorer
+ * (plain FF/BF/WF only, see vsbpp_pack_batch_ex) */
+enum { VSBPP_TYPE_SMALLEST_FIT = 0, VSBPP_TYPE_LARGEST = 1, VSBPP_TYPE_LEARNED = 2 };
 
 enum {
   VSBPP_OK = 0,
@@ -215,6 +216,128 @@ int32_t vsbpp_plan_run(vsbpp_plan* plan, void* hip_stream);
 int32_t vsbpp_plan_launch(const vsbpp_plan* plan, vsbpp_launch* out);
 /* Releases the plan, its workspace and graph (after outstanding runs). */
 void vsbpp_plan_destroy(vsbpp_plan* plan);
+
+/* ------------------------------------------------------------------------ */
+/* Learned bin-type scorer.                                                  */
+/*                                                                            */
+/* A decision is an item that fits no open bin in a plain FF/BF/WF run; the  */
+/* scorer proposes the type of the bin it opens, among the types that hold   */
+/* the item.  Capacity checks stay exact integer; a non-finite score falls   */
+/* back to the smallest fitting type, and that plain rule is the baseline    */
+/* the scorer's cost is judged against.                                      */
+/*                                                                            */
+/* Decision features (fp32), for item w at position q of m, before the bin  */
+/* opens:                                                                     */
+/*   0  w / B_1                                                               */
+/*   1  (m - q - 1) / m                                                       */
+/*   2  mean weight of the items after q / B_1 (0 if none)                    */
+/*   3  smallest weight after q / B_1 (1 if none)                             */
+/*   4  bins opened so far / m                                                */
+/*   5..10  share of the bins opened so far whose room r falls in bucket     */
+/*          floor(6 r / (B_1 + 1)) = 0..5                                     */
+/*   11..14 B_2 .. B_5 over B_1 (0 beyond n)                                  */
+/*   15 w / (smallest capacity >= w)                                          */
+/* Network: h1 = relu(W1 x + b1) (64), h2 = relu(W2 h1 + b2) (64),           */
+/* z = W3 h2 + b3 (n_out); every output is its bias followed by a chain of   */
+/* fp32 fused multiply-adds over the inputs in index order, so results are   */
+/* reproducible bit for bit.  Decision: the type k < min(n, n_out) holding   */
+/* the item with the largest z, lowest k on ties.                            */
+/* ------------------------------------------------------------------------ */
+
+#define VSBPP_NFEAT 16
+#define VSBPP_HIDDEN 64
+#define VSBPP_MAX_OUT 16
+
+/* Weights as bfloat16 bit patterns, biases fp32, row-major [out][in]. */
+typedef struct vsbpp_model {
+  int32_t n_out;
+  uint16_t w1[VSBPP_HIDDEN * VSBPP_NFEAT];
+  float b1[VSBPP_HIDDEN];
+  uint16_t w2[VSBPP_HIDDEN * VSBPP_HIDDEN];
+  float b2[VSBPP_HIDDEN];
+  uint16_t w3[VSBPP_MAX_OUT * VSBPP_HIDDEN];
+  float b3[VSBPP_MAX_OUT];
+} vsbpp_model;
+
+/* Decision hooks of a plain FF/BF/WF batch (all device pointers, each may be
+ * NULL).  Entry e of the batch reads the inputs of instance src[e] (the
+ * batch's CSR arrays, weights/capacities/order/seed) -- so one instance can
+ * be packed by many entries -- and writes d_nbins[e] and d_cost[e].  With
+ * src set, the assignment and bin-type outputs are not written (they may be
+ * NULL).  force[3e..3e+2] = (d, t1, t2): the bin opened at decision d of
+ * entry e gets type t1 and the one at decision d+1 type t2 (a type that does
+ * not hold the item is ignored; d = -1 forces nothing).  At decision d,
+ * features[16e..16e+15] receive the decision features and info[2e] the mask
+ * of types holding the item (bit k for B_k >= w), info[2e+1] the smallest
+ * fitting type; entries whose run has no decision d leave them untouched. */
+typedef struct vsbpp_decisions {
+  const int32_t* src;
+  const int32_t* force;
+  float* features;
+  int32_t* info;
+} vsbpp_decisions;
+
+/* vsbpp_pack_batch with a scorer (d_model: device pointer to a vsbpp_model,
+ * required when opt->type_rule is VSBPP_TYPE_LEARNED, else ignored) and
+ * decision hooks (dec may be NULL).  Plain FF/BF/WF only when either is
+ * used.  Asynchronous on hip_stream, no allocation. */
+int32_t vsbpp_pack_batch_ex(const vsbpp_batch* batch, int32_t heuristic,
+                            const vsbpp_options* opt, const vsbpp_model* d_model,
+                            const vsbpp_decisions* dec, void* hip_stream);
+
+/* Depth-2 lookahead labels from rollout costs.  d_cost holds, for decision
+ * i, k1 and k2 in [0, n_types), the cost of the run with k1 forced at the
+ * decision and k2 at the next one, at index (i*n_types + k1)*n_types + k2;
+ * d_info holds the (feasible mask, smallest fitting type) pair of each
+ * decision.  V(k1) = min over k2; the label is argmin over feasible k1 of V,
+ * ties to the smallest fitting type when it is among them, else the lowest
+ * type.  Writes d_labels[num_decisions] (and d_values[num*n_types] with -1
+ * for infeasible types, when not NULL). */
+int32_t vsbpp_rollout_labels(const int64_t* d_cost, const int32_t* d_info,
+                             int32_t num_decisions, int32_t n_types, int32_t* d_labels,
+                             int64_t* d_values, void* hip_stream);
+
+/* Training of the scorer on the GPU: fp32 master weights, bfloat16 working
+ * weights (round to nearest even after every step), forward and backward
+ * with fp32 accumulation, masked softmax cross-entropy over the feasible
+ * types, Adam.  Gradients are summed over the minibatch (mean over its
+ * samples) in a fixed order, so training is deterministic. */
+typedef struct vsbpp_trainer vsbpp_trainer;
+
+/* init: host model holding the initial weights (their fp32 values are the
+ * bf16 ones); n_out in 1..16. */
+int32_t vsbpp_trainer_create(const vsbpp_model* init, vsbpp_trainer** out);
+/* One step on the minibatch d_idx[batch] of the training set d_x[N*16]
+ * (features), d_mask[N] (feasible types), d_label[N]; lr, beta1, beta2, eps
+ * as in Adam.  *out_loss (host, may be NULL) receives the minibatch mean
+ * loss after the step's forward pass (this synchronises).  Asynchronous
+ * otherwise. */
+int32_t vsbpp_trainer_step(vsbpp_trainer* tr, const float* d_x, const int32_t* d_mask,
+                           const int32_t* d_label, const int32_t* d_idx, int32_t batch,
+                           float lr, float beta1, float beta2, float eps, float* out_loss,
+                           void* hip_stream);
+/* Gradient of the mean loss over the minibatch at the current weights,
+ * without an update: host out[] in the order w1, b1, w2, b2, w3 (n_out rows),
+ * b3 (n_out); returns the number of values written.  Synchronous. */
+int32_t vsbpp_trainer_gradient(vsbpp_trainer* tr, const float* d_x, const int32_t* d_mask,
+                               const int32_t* d_label, const int32_t* d_idx, int32_t batch,
+                               float* out, int32_t out_cap);
+/* Device pointer to the current bf16 model (for vsbpp_pack_batch_ex). */
+const vsbpp_model* vsbpp_trainer_device_model(const vsbpp_trainer* tr);
+/* Copies the current bf16 model to host memory (synchronous). */
+int32_t vsbpp_trainer_export(const vsbpp_trainer* tr, vsbpp_model* out);
+void vsbpp_trainer_destroy(vsbpp_trainer* tr);
+
+/* Lower bounds of the optimum of every instance of a device CSR batch (the
+ * denominator of the cost/LB quality figure): d_out[3i] = total weight,
+ * d_out[3i+1] = LB_cap, the least total >= the weight that is a sum of
+ * capacities with repetition (exact when the smallest capacity is <= 8192,
+ * else the total weight), d_out[3i+2] = LB_big, the sum over items heavier
+ * than B_1/2 of the smallest capacity holding them.  LB = max(LB_cap, LB_big).
+ * An instance with m < 1 or n outside 1..16 gets -1s.  Asynchronous. */
+int32_t vsbpp_lower_bounds(int32_t num, const int32_t* d_weights, const int64_t* d_item_off,
+                           const int32_t* d_capacities, const int32_t* d_cap_off, int64_t* d_out,
+                           void* hip_stream);
 
 /* Best of a batch: writes d_out[0] = min cost and d_out[1] = the lowest index
  * reaching it over d_cost[0..num-1] (device pointers, asynchronous on

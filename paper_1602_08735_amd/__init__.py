@@ -32,6 +32,9 @@ EXPORTS = (
     "vsbpp_options_init", "vsbpp_pack", "vsbpp_pack_ex", "vsbpp_pack_batch",
     "vsbpp_best_of", "vsbpp_strerror", "vsbpp_device_ok", "vsbpp_plan_create",
     "vsbpp_plan_run", "vsbpp_plan_launch", "vsbpp_plan_destroy", "vsbpp_last_error",
+    "vsbpp_pack_batch_ex", "vsbpp_rollout_labels", "vsbpp_trainer_create",
+    "vsbpp_trainer_step", "vsbpp_trainer_gradient", "vsbpp_trainer_device_model",
+    "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
 )
 
 
@@ -293,6 +296,184 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             _plan_lib().vsbpp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Learned bin-type scorer
+# ---------------------------------------------------------------------------
+TYPE_LEARNED = 2
+NFEAT, HIDDEN, MAX_OUT = 16, 64, 16
+
+
+class Model(ctypes.Structure):
+    """vsbpp_model: bf16 weight bit patterns, fp32 biases, row-major [out][in]."""
+    _fields_ = [
+        ("n_out", ctypes.c_int32),
+        ("w1", ctypes.c_uint16 * (HIDDEN * NFEAT)),
+        ("b1", ctypes.c_float * HIDDEN),
+        ("w2", ctypes.c_uint16 * (HIDDEN * HIDDEN)),
+        ("b2", ctypes.c_float * HIDDEN),
+        ("w3", ctypes.c_uint16 * (MAX_OUT * HIDDEN)),
+        ("b3", ctypes.c_float * MAX_OUT),
+    ]
+
+    def to_bytes(self) -> bytes:
+        return bytes(self)
+
+    @classmethod
+    def from_bytes(cls, data: bytes) -> "Model":
+        m = cls()
+        ctypes.memmove(ctypes.addressof(m), data, ctypes.sizeof(cls))
+        return m
+
+
+class _Decisions(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("force", ctypes.c_void_p),
+                ("features", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
+def _learn_lib():
+    L = _plan_lib()
+    if not getattr(L, "_learn_ready", False):
+        vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+        L.vsbpp_pack_batch_ex.restype = i32
+        L.vsbpp_pack_batch_ex.argtypes = [ctypes.POINTER(_BatchDesc), i32, ctypes.POINTER(Options),
+                                          vp, ctypes.POINTER(_Decisions), vp]
+        L.vsbpp_rollout_labels.restype = i32
+        L.vsbpp_rollout_labels.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        L.vsbpp_trainer_create.restype = i32
+        L.vsbpp_trainer_create.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(vp)]
+        L.vsbpp_trainer_step.restype = i32
+        L.vsbpp_trainer_step.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32,
+                                         ctypes.POINTER(f32), vp]
+        L.vsbpp_trainer_gradient.restype = i32
+        L.vsbpp_trainer_gradient.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32]
+        L.vsbpp_trainer_device_model.restype = vp
+        L.vsbpp_trainer_device_model.argtypes = [vp]
+        L.vsbpp_trainer_export.restype = i32
+        L.vsbpp_trainer_export.argtypes = [vp, ctypes.POINTER(Model)]
+        L.vsbpp_trainer_destroy.restype = None
+        L.vsbpp_trainer_destroy.argtypes = [vp]
+        L.vsbpp_lower_bounds.restype = i32
+        L.vsbpp_lower_bounds.argtypes = [i32, vp, vp, vp, vp, vp, vp]
+        L._learn_ready = True
+    return L
+
+
+def _desc(db: DeviceBatch, use_order=True, use_seeds=True, outputs=True, num=None):
+    ptr = lambda x: None if x is None else x.data_ptr()
+    return _BatchDesc(
+        db.n if num is None else num, ptr(db.weights), ptr(db.item_off), ptr(db.caps),
+        ptr(db.cap_off), ptr(db.order) if use_order else None,
+        ptr(db.seeds) if use_seeds else None, db.max_items, db.max_types, db.max_cap,
+        ptr(db.assignment) if outputs else None, ptr(db.bin_types) if outputs else None,
+        ptr(db.nbins), ptr(db.cost))
+
+
+def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force=None,
+                  features=None, info=None, nbins=None, cost=None, seed: int = 0,
+                  type_rule: int = TYPE_SMALLEST_FIT, stream=None) -> None:
+    """vsbpp_pack_batch_ex.  With `src` (int32 tensor [E]) the batch has E
+    entries reading instance src[e]; nbins/cost then receive E results (pass
+    tensors of size E)."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    L = _learn_lib()
+    ptr = lambda x: None if x is None else x.data_ptr()
+    d = _desc(db, outputs=src is None, num=(src.numel() if src is not None else None))
+    if nbins is not None:
+        d.nbins = nbins.data_ptr()
+    if cost is not None:
+        d.cost = cost.data_ptr()
+    dec = _Decisions(ptr(src), ptr(force), ptr(features), ptr(info))
+    o = options(seed, type_rule=type_rule)
+    rc = L.vsbpp_pack_batch_ex(ctypes.byref(d), _heur(heuristic), ctypes.byref(o), model_ptr,
+                               ctypes.byref(dec), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_pack_batch_ex")
+
+
+def rollout_labels(cost, info, num: int, n_types: int, labels, values=None, stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _learn_lib().vsbpp_rollout_labels(
+        cost.data_ptr(), info.data_ptr(), num, n_types, labels.data_ptr(),
+        None if values is None else values.data_ptr(), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_rollout_labels")
+
+
+def lower_bounds(db: DeviceBatch, out, stream=None):
+    """out: int64 tensor [3*N] <- (sum of weights, LB_cap, LB_big) per instance."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _learn_lib().vsbpp_lower_bounds(db.n, db.weights.data_ptr(), db.item_off.data_ptr(),
+                                         db.caps.data_ptr(), db.cap_off.data_ptr(),
+                                         out.data_ptr(), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_lower_bounds")
+
+
+class Trainer:
+    """GPU trainer of the scorer (vsbpp_trainer_*)."""
+
+    def __init__(self, init: Model):
+        L = _learn_lib()
+        h = ctypes.c_void_p()
+        rc = L.vsbpp_trainer_create(ctypes.byref(init), ctypes.byref(h))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_trainer_create")
+        self._h = h
+        self.n_out = init.n_out
+
+    @property
+    def device_model(self):
+        return _learn_lib().vsbpp_trainer_device_model(self._h)
+
+    def step(self, x, mask, label, idx, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+             want_loss=False, stream=None):
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        loss = ctypes.c_float(0.0)
+        rc = _learn_lib().vsbpp_trainer_step(
+            self._h, x.data_ptr(), mask.data_ptr(), label.data_ptr(), idx.data_ptr(),
+            idx.numel(), lr, beta1, beta2, eps, ctypes.byref(loss) if want_loss else None,
+            ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_trainer_step")
+        return float(loss.value) if want_loss else None
+
+    def gradient(self, x, mask, label, idx) -> np.ndarray:
+        np_ = 1024 + 64 + 4096 + 64 + 65 * self.n_out
+        out = np.zeros(np_, dtype=np.float32)
+        rc = _learn_lib().vsbpp_trainer_gradient(self._h, x.data_ptr(), mask.data_ptr(),
+                                                 label.data_ptr(), idx.data_ptr(), idx.numel(),
+                                                 out.ctypes.data, np_)
+        if rc < 0:
+            raise VsbppError(rc, "vsbpp_trainer_gradient")
+        return out
+
+    def export(self) -> Model:
+        m = Model()
+        rc = _learn_lib().vsbpp_trainer_export(self._h, ctypes.byref(m))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_trainer_export")
+        return m
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _learn_lib().vsbpp_trainer_destroy(self._h)
             self._h = None
 
     def __del__(self):

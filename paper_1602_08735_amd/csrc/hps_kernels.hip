@@ -16,6 +16,8 @@
 // four bins and lanes are unit-stride.  Output bin ids are canonical: used
 // bins (load > 0) in creation order, packers in sublist/subset order; the
 // per-instance id offsets come from a block scan over the packers.
+#include <type_traits>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -377,7 +379,9 @@ template <typename K>
 __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_caps[kMaxTypes];
-  __shared__ uint64_t s_wmin[16];
+  using GK = typename std::conditional<sizeof(K) == 4, uint32_t, uint64_t>::type;
+  constexpr int kRankBits = sizeof(K) == 4 ? 10 : 16;
+  __shared__ GK s_wmin[16];
   __shared__ int s_flag;
   const int tid = threadIdx.x, B = blockDim.x;
   const int spr = B / group;  // subsets per round
@@ -427,6 +431,8 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
     const int S = min(a.s2, m);
     const int P = factorial_small(S);
     const int l = (m + S - 1) / S;
+    // permutation of rank r of a full subset (the same for every subset)
+    const uint32_t pm_full = r < P ? nth_perm(r, S) : 0u;
     int32_t carry = 0;
     int64_t cost_acc = 0;
     for (int base_I = 0; base_I < l; base_I += spr) {
@@ -443,13 +449,13 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
         s_w[g * kMaxSubset + r] = a.w[off + item];
       }
       __syncthreads();
-      uint64_t key = ~0ull;
+      GK key = ~(GK)0;
       uint64_t locs = 0;
       uint64_t u = 0;
       int64_t c = 0;
       if (active) {
         pk.init(s_caps, n, nbslots);
-        const uint32_t pm = nth_perm(r, k);
+        const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
           const int32_t w = s_w[g * kMaxSubset + d];
@@ -461,14 +467,14 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
           locs |= (uint64_t)b << (6 * d);
         }
         u = pk.used(&c);
-        key = ((uint64_t)c << 16) | (uint64_t)r;
+        key = ((GK)c << kRankBits) | (GK)r;
       }
       // group minimum of (cost, rank): lowest rank on ties
-      uint64_t gm = wave_min(key);
+      GK gm = wave_min(key);
       if (wpg > 1) {
         if (lane == 0) s_wmin[wave] = gm;
         __syncthreads();
-        gm = ~0ull;
+        gm = ~(GK)0;
         for (int i = 0; i < wpg; ++i) gm = min(gm, s_wmin[g * wpg + i]);
       }
       if (active && key == gm) {

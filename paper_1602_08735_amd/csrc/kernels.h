@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/vsbpp.h"
+
 namespace vsbpp {
 
 // error codes written to nbins[i] for instances that fail device-side checks
@@ -35,6 +37,12 @@ struct BatchArgs {
   int32_t slots;            // plain kernel: LDS key slots per wavefront
   int32_t* queue;           // persistent mode: work counter (zeroed before the launch), or null
   const int32_t* sched;     // optional processing order of the instances (LPT), or null
+  // decision hooks and the scorer (plain FF/BF/WF only)
+  const int32_t* src;       // entry -> source instance, or null
+  const int32_t* force;     // [3*num] (d, t1, t2), or null
+  float* feat_out;          // [16*num], or null
+  int32_t* info_out;        // [2*num], or null
+  const vsbpp_model* model; // type_rule 2
 };
 
 // Next instance for a wavefront (plain kernel) or a workgroup (H1/H2): a
@@ -64,7 +72,12 @@ constexpr int kStaticLdsReserve = 1024;
 // Launch helpers (defined next to their kernels).  They return a hipError_t.
 hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int waves_per_block,
                         size_t lds_per_wave, hipStream_t s);
-size_t plain_lds_per_wave(int slots, int max_items, bool wide);
+// ext: decision hooks or the scorer in use
+size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext = false);
+size_t plain_lds_block_extra(bool learned);
+inline bool plain_ext(const BatchArgs& a) {
+  return a.src || a.force || a.feat_out || a.info_out || a.type_rule == 2;
+}
 size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide);
 size_t h2_lds_bytes(int nbslots, int block, int group, bool wide);
 int h2_group(int s2);
@@ -73,6 +86,12 @@ hipError_t launch_h1(const BatchArgs& a, bool wide, int nb_regs, int block_threa
 hipError_t launch_h2(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
                      hipStream_t s);
 hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStream_t s);
+
+// per-instance (sum of weights, LB_cap, LB_big); LB_cap is exact when the
+// smallest capacity is <= 8192, else the sum of weights
+hipError_t launch_bounds(int32_t num, const int32_t* w, const int64_t* item_off,
+                         const int32_t* caps, const int32_t* cap_off, int64_t* out,
+                         hipStream_t s);
 
 // scheduling helpers
 hipError_t launch_queue_reset(int32_t* queue, hipStream_t s);
@@ -88,7 +107,8 @@ hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nb_regs, int block_
 hipError_t launch_h2_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
                           int grid, hipStream_t s);
 // resident workgroups per CU for a launch shape (for persistent grids)
-int plain_blocks_per_cu(int crit, bool wide, int waves_per_block, size_t lds_per_wave);
+int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int waves_per_block,
+                        size_t lds_per_wave);
 int h1_blocks_per_cu(bool wide, int block_threads, size_t lds);
 int h2_blocks_per_cu(bool wide, int block_threads, size_t lds);
 

@@ -127,7 +127,104 @@ __device__ int compact(K* keys, typename KeyT<K>::Pid* pid, int nlive, int32_t T
   return newn;
 }
 
-template <int CRIT, typename K>
+// ---------------------------------------------------------------------------
+// Learned bin-type scorer, evaluated by one wavefront: lane l computes hidden
+// unit l (and output l & 15); every output is its bias followed by an fp32
+// fused-multiply-add chain over its inputs in index order.  The model is
+// staged once per workgroup in LDS with 8 consecutive bf16 weights of one
+// output row per 16-byte word, rows of a column block adjacent, so the 64
+// lanes read unit-stride.
+// ---------------------------------------------------------------------------
+struct ModelLds {
+  uint16_t w1[2 * 64 * 8];   // [i/8][l][8]
+  uint16_t w2[8 * 64 * 8];   // [j/8][l][8]
+  uint16_t w3[8 * 16 * 8];   // [j/8][k][8]
+  float b1[64], b2[64], b3[16];
+};
+
+__device__ __forceinline__ float bf16f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+__device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
+  for (int e = threadIdx.x; e < 64 * 16; e += blockDim.x) {
+    const int l = e >> 4, i = e & 15;
+    s->w1[(((i >> 3) * 64) + l) * 8 + (i & 7)] = m->w1[e];
+  }
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    const int l = e >> 6, j = e & 63;
+    s->w2[(((j >> 3) * 64) + l) * 8 + (j & 7)] = m->w2[e];
+  }
+  for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+    const int k = e >> 6, j = e & 63;
+    s->w3[(((j >> 3) * 16) + k) * 8 + (j & 7)] = m->w3[e];
+  }
+  for (int e = threadIdx.x; e < 64; e += blockDim.x) {
+    s->b1[e] = m->b1[e];
+    s->b2[e] = m->b2[e];
+    if (e < 16) s->b3[e] = m->b3[e];
+  }
+}
+
+// z for this lane's output (lane & 15); x are wave-uniform features, hbuf a
+// 64-float LDS scratch of this wavefront.
+__device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], float* hbuf,
+                                  int lane) {
+  float acc = md->b1[lane];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib) {
+    const uint4 wv = *reinterpret_cast<const uint4*>(&md->w1[(ib * 64 + lane) * 8]);
+    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      acc = __builtin_fmaf(bf16f((wr[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu), x[ib * 8 + r], acc);
+  }
+  hbuf[lane] = acc > 0.0f ? acc : 0.0f;
+  acc = md->b2[lane];
+#pragma unroll
+  for (int jb = 0; jb < 8; ++jb) {
+    const uint4 wv = *reinterpret_cast<const uint4*>(&md->w2[(jb * 64 + lane) * 8]);
+    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
+    const float4 h0 = *reinterpret_cast<const float4*>(&hbuf[jb * 8]);
+    const float4 h1 = *reinterpret_cast<const float4*>(&hbuf[jb * 8 + 4]);
+    const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      acc = __builtin_fmaf(bf16f((wr[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu), hv[r], acc);
+  }
+  const float h2 = acc > 0.0f ? acc : 0.0f;
+  hbuf[lane] = h2;
+  const int k = lane & 15;
+  acc = md->b3[k];
+#pragma unroll
+  for (int jb = 0; jb < 8; ++jb) {
+    const uint4 wv = *reinterpret_cast<const uint4*>(&md->w3[(jb * 16 + k) * 8]);
+    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
+    const float4 h0 = *reinterpret_cast<const float4*>(&hbuf[jb * 8]);
+    const float4 h1 = *reinterpret_cast<const float4*>(&hbuf[jb * 8 + 4]);
+    const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      acc = __builtin_fmaf(bf16f((wr[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu), hv[r], acc);
+  }
+  return acc;
+}
+
+// inclusive suffix minimum over lanes [lane, 63]
+__device__ __forceinline__ int32_t wave_suffix_min(int32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t o = __shfl_down(v, d, kWave);
+    if (lane + d < kWave) v = min(v, o);
+  }
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+template <int CRIT, typename K, bool EXT>
 __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per_wave) {
   using KT = KeyT<K>;
   using Pid = typename KT::Pid;
@@ -139,6 +236,16 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   const size_t pid_bytes = ((size_t)a.slots * sizeof(Pid) + 15) & ~(size_t)15;
   Pid* pid = reinterpret_cast<Pid*>(base + (size_t)a.slots * sizeof(K));
   int32_t* smin = reinterpret_cast<int32_t*>(base + (size_t)a.slots * sizeof(K) + pid_bytes);
+  const size_t smin_bytes = (((size_t)a.max_items + 63) / 64 * 4 + 15) & ~(size_t)15;
+  int32_t* hist = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(smin) + smin_bytes);
+  float* hbuf = reinterpret_cast<float*>(hist + 16);
+  ModelLds* md = reinterpret_cast<ModelLds*>(smem + (size_t)wpb * lds_per_wave);
+  if constexpr (EXT) {
+    if (a.type_rule == 2) {
+      stage_model(a.model, md);
+      __syncthreads();
+    }
+  }
 
   int cursor = blockIdx.x * wpb + wave;
   for (;;) {
@@ -153,10 +260,12 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
     }
     if (slot >= a.num) break;
     const int inst = a.sched ? uniform(a.sched[slot]) : slot;
-    const int64_t off = a.item_off[inst];
-    const int64_t m64 = a.item_off[inst + 1] - off;
-    const int c0 = a.cap_off[inst];
-    const int n = a.cap_off[inst + 1] - c0;
+    // inputs come from instance `src_i` (entries may share an instance)
+    const int src_i = (EXT && a.src) ? uniform(a.src[inst]) : inst;
+    const int64_t off = a.item_off[src_i];
+    const int64_t m64 = a.item_off[src_i + 1] - off;
+    const int c0 = a.cap_off[src_i];
+    const int n = a.cap_off[src_i + 1] - c0;
     int err = 0;
     if (m64 < 1 || m64 > a.max_items || n < 1 || n > kMaxTypes || n > a.max_types)
       err = kErrSize;
@@ -170,6 +279,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
     }
     const int m = (int)m64;
     const int nch = (m + 63) >> 6;
+    int64_t total = 0;
     if (!err) {
       // validation and per-chunk suffix minima of the weights in position order
       bool badw = false, bado = false;
@@ -194,6 +304,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
         }
         run = min(run, wave_min(wq));
         if (lane == 0) smin[c] = run;
+        if constexpr (EXT) total += wave_sum64(q < m ? (int64_t)wq : 0);
       }
       if (ballot(badw)) err = kErrWeight;
       else if (ballot(bado)) err = kErrOption;
@@ -205,6 +316,28 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
       }
       continue;
     }
+    // decision state (extended runs only)
+    int fd = -1, ft1 = -1, ft2 = -1, nev = 0;
+    int64_t placed = 0;
+    int32_t thr[5] = {0, 0, 0, 0, 0};
+    if constexpr (EXT) {
+      if (a.force) {
+        fd = uniform(a.force[3 * (int64_t)inst]);
+        ft1 = uniform(a.force[3 * (int64_t)inst + 1]);
+        ft2 = uniform(a.force[3 * (int64_t)inst + 2]);
+      }
+      // room r is in bucket floor(6r/(B_1+1)) = number of k in 1..5 with
+      // r >= ceil(k(B_1+1)/6)
+#pragma unroll
+      for (int k = 1; k <= 5; ++k) thr[k - 1] = (int32_t)(((int64_t)k * (B1 + 1) + 5) / 6);
+      if (lane < 8) hist[lane] = 0;
+    }
+    auto bucket = [&](int64_t r) -> int {
+      int b = 0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) b += r >= thr[k] ? 1 : 0;
+      return b;
+    };
 
     int nlive = 0, nb = 0, dead = 0;
     int32_t tprev = 0;
@@ -224,6 +357,11 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
         if (a.order) item = a.order[off + q];
         wv = a.w[off + item];
       }
+      int32_t sfx = 0x7FFFFFFF, next_min = 0x7FFFFFFF;
+      if constexpr (EXT) {
+        sfx = wave_suffix_min(q < m ? wv : 0x7FFFFFFF, lane);
+        if (c + 1 < nch) next_min = uniform(smin[c + 1]);
+      }
       // positions are stable until the next compaction, so each item records
       // its bin's position and the ids are read once at the end of the chunk
       int32_t mypos = 0;
@@ -235,19 +373,25 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
         K nk = 0;
         const int ng = uniform((nlive + 255) >> 8);
         if constexpr (CRIT == FF) {
-          for (int g = 0; g < ng && p < 0; ++g) {
-            K k[4];
-            load_group(keys, g, lane, k);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const uint64_t fm = ballot(k[j] >= wk);
-              if (fm) {
-                const int l = __builtin_ctzll(fm);
-                p = (g << 8) + (j << 6) + l;
-                nk = readlane(k[j], l) - wk;
-                break;
-              }
+          // groups in position order; the next group's keys are loaded while
+          // the four 64-bin rows of the current one are tested
+          K k[4], kn[4];
+          if (ng > 0) load_group(keys, 0, lane, k);
+          for (int g = 0; g < ng; ++g) {
+            if (g + 1 < ng) load_group(keys, g + 1, lane, kn);
+            const uint64_t f0 = ballot(k[0] >= wk), f1 = ballot(k[1] >= wk);
+            const uint64_t f2 = ballot(k[2] >= wk), f3 = ballot(k[3] >= wk);
+            if (f0 | f1 | f2 | f3) {
+              const int j = f0 ? 0 : (f1 ? 1 : (f2 ? 2 : 3));
+              const uint64_t fm = f0 ? f0 : (f1 ? f1 : (f2 ? f2 : f3));
+              const int l = __builtin_ctzll(fm);
+              p = (g << 8) + (j << 6) + l;
+              const K kj = j == 0 ? k[0] : (j == 1 ? k[1] : (j == 2 ? k[2] : k[3]));
+              nk = readlane(kj, l) - wk;
+              break;
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[j] = kn[j];
           }
         } else {
           K best = ~(K)0;
@@ -277,11 +421,84 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
         if (p >= 0) {
           // Rule 4: place into the chosen open bin
           if (lane == (p & 63)) keys[kidx(p)] = nk;
-          if (room_of<CRIT>(nk) < (K)T) ++dead;
+          const K rnew = room_of<CRIT>(nk);
+          if (rnew < (K)T) ++dead;
+          if constexpr (EXT) {
+            const int b0 = bucket((int64_t)rnew + w), b1 = bucket((int64_t)rnew);
+            if (b0 != b1 && lane == 0) {
+              atomicAdd(&hist[b0], -1);
+              atomicAdd(&hist[b1], 1);
+            }
+          }
         } else {
           // nothing fits: open a bin of the chosen type
           const uint64_t fm = ballot(lane < n && cap_lane >= w);
-          const int t = a.type_rule == 1 ? 0 : (int)__popcll(fm) - 1;
+          const int smallest = (int)__popcll(fm) - 1;
+          int t = a.type_rule == 1 ? 0 : smallest;
+          if constexpr (EXT) {
+            const int d = nev;
+            nev = uniform(nev + 1);
+            const bool dump = d == fd && (a.feat_out || a.info_out);
+            if (a.type_rule == 2 || dump) {
+              // decision features (wave-uniform values)
+              const int qq = (c << 6) + jj;
+              const int rem = m - qq - 1;
+              const int64_t rsum = total - placed - w;
+              int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
+              after = min(after, next_min);
+              const float fb1 = (float)B1;
+              float x[16];
+              x[0] = (float)w / fb1;
+              x[1] = (float)rem / (float)m;
+              x[2] = rem > 0 ? (float)rsum / (float)((int64_t)rem * (int64_t)B1) : 0.0f;
+              x[3] = rem > 0 ? (float)after / fb1 : 1.0f;
+              x[4] = (float)nb / (float)m;
+              const float den = (float)(nb > 0 ? nb : 1);
+              const int4 h03 = *reinterpret_cast<const int4*>(hist);
+              const int4 h47 = *reinterpret_cast<const int4*>(hist + 4);
+              x[5] = (float)h03.x / den;
+              x[6] = (float)h03.y / den;
+              x[7] = (float)h03.z / den;
+              x[8] = (float)h03.w / den;
+              x[9] = (float)h47.x / den;
+              x[10] = (float)h47.y / den;
+#pragma unroll
+              for (int k = 1; k <= 4; ++k)
+                x[10 + k] = k < n ? (float)readlane(cap_lane, k) / fb1 : 0.0f;
+              x[15] = (float)w / (float)readlane(cap_lane, smallest);
+              if (a.type_rule == 2) {
+                const float z = mlp_forward_wave(md, x, hbuf, lane);
+                const int kmax = min(n, (int)a.model->n_out);
+                float zb = __uint_as_float(readlane(__float_as_uint(z), 0));
+                bool fin = __builtin_isfinite(zb);
+                int bi = 0;
+                for (int k = 1; k < kmax; ++k) {
+                  const float zk = __uint_as_float(readlane(__float_as_uint(z), k));
+                  fin = fin && __builtin_isfinite(zk);
+                  if (((fm >> k) & 1ull) && zk > zb) {
+                    zb = zk;
+                    bi = k;
+                  }
+                }
+                // the scorer only proposes: non-finite scores fall back
+                t = fin ? bi : smallest;
+              }
+              if (dump) {
+                if (a.feat_out && lane < 16) {
+                  float xv = 0.0f;
+#pragma unroll
+                  for (int k = 0; k < 16; ++k) xv = lane == k ? x[k] : xv;
+                  a.feat_out[16 * (int64_t)inst + lane] = xv;
+                }
+                if (a.info_out && lane == 0) {
+                  a.info_out[2 * (int64_t)inst] = (int32_t)fm;
+                  a.info_out[2 * (int64_t)inst + 1] = smallest;
+                }
+              }
+            }
+            const int ft = d == fd ? ft1 : (fd >= 0 && d == fd + 1 ? ft2 : -1);
+            if (ft >= 0 && ft < n && ((fm >> ft) & 1ull)) t = ft;
+          }
           const int32_t Bt = readlane(cap_lane, t);
           const K room = (K)(Bt - w);
           p = nlive;
@@ -292,16 +509,22 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
           const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)p) : ((room << KT::SH) | (K)p);
           if (lane == (p & 63)) keys[kidx(p)] = key;
           if (lane == 0) pid[p] = (Pid)id;
+          const bool out_types = !EXT || !a.src;
           typebuf = lane == (id & 63) ? t : typebuf;
-          if ((id & 63) == 63) a.types[off + (id - 63) + lane] = typebuf;
+          if (out_types && (id & 63) == 63) a.types[off + (id - 63) + lane] = typebuf;
           cost += Bt;
           if (room < (K)T) ++dead;
+          if constexpr (EXT) {
+            if (lane == 0) atomicAdd(&hist[bucket((int64_t)room)], 1);
+          }
         }
+        if constexpr (EXT) placed += w;
         mypos = lane == jj ? p : mypos;
       }
-      if (q < m) a.assign[off + item] = (int32_t)pid[mypos];
+      if ((!EXT || !a.src) && q < m) a.assign[off + item] = (int32_t)pid[mypos];
     }
-    if ((nb & 63) && lane < (nb & 63)) a.types[off + (nb & ~63) + lane] = typebuf;
+    if ((!EXT || !a.src) && (nb & 63) && lane < (nb & 63))
+      a.types[off + (nb & ~63) + lane] = typebuf;
     if (lane == 0) {
       a.nbins[inst] = nb;
       a.cost[inst] = cost;
@@ -309,10 +532,10 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   }
 }
 
-template <int CRIT, typename K>
+template <int CRIT, typename K, bool EXT>
 hipError_t launch_one(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid, hipStream_t s) {
-  const size_t lds = lds_per_wave * (size_t)wpb;
-  auto kern = k_plain<CRIT, K>;
+  const size_t lds = lds_per_wave * (size_t)wpb + (EXT ? plain_lds_block_extra(a.type_rule == 2) : 0);
+  auto kern = k_plain<CRIT, K, EXT>;
   static bool raised = false;
   if (lds > 65536 && !raised) {
     hipError_t e = allow_max_dynamic_lds(kern);
@@ -325,36 +548,49 @@ hipError_t launch_one(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid
 }
 
 template <int CRIT, typename K>
-int occupancy(int wpb, size_t lds_per_wave) {
+hipError_t launch_sel(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid, hipStream_t s) {
+  return plain_ext(a) ? launch_one<CRIT, K, true>(a, wpb, lds_per_wave, grid, s)
+                      : launch_one<CRIT, K, false>(a, wpb, lds_per_wave, grid, s);
+}
+
+template <int CRIT, typename K>
+int occupancy(int wpb, size_t lds_per_wave, bool ext, bool learned) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K>, 64 * wpb,
-                                                    lds_per_wave * (size_t)wpb) != hipSuccess)
-    return 1;
+  const size_t lds = lds_per_wave * (size_t)wpb + (ext ? plain_lds_block_extra(learned) : 0);
+  const hipError_t e =
+      ext ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true>, 64 * wpb, lds)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false>, 64 * wpb, lds);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
 }  // namespace
 
-size_t plain_lds_per_wave(int slots, int max_items, bool wide) {
+size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext) {
   const size_t ks = wide ? 8 : 4, ps = wide ? 4 : 2;
   const size_t nch = ((size_t)max_items + 63) / 64;
   size_t b = (size_t)slots * ks;
   b += ((size_t)slots * ps + 15) & ~(size_t)15;
   b += (nch * 4 + 15) & ~(size_t)15;
+  if (ext) b += 16 * 4 + 64 * 4;  // room histogram + hidden-layer scratch
   return b;
+}
+
+size_t plain_lds_block_extra(bool learned) {
+  return learned ? ((sizeof(ModelLds) + 15) & ~(size_t)15) : 0;
 }
 
 hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
                              size_t lds_per_wave, int grid, hipStream_t s) {
   if (a.num <= 0) return hipSuccess;
   if (!wide) {
-    if (crit == FF) return launch_one<FF, uint32_t>(a, wpb, lds_per_wave, grid, s);
-    if (crit == BF) return launch_one<BF, uint32_t>(a, wpb, lds_per_wave, grid, s);
-    return launch_one<WF, uint32_t>(a, wpb, lds_per_wave, grid, s);
+    if (crit == FF) return launch_sel<FF, uint32_t>(a, wpb, lds_per_wave, grid, s);
+    if (crit == BF) return launch_sel<BF, uint32_t>(a, wpb, lds_per_wave, grid, s);
+    return launch_sel<WF, uint32_t>(a, wpb, lds_per_wave, grid, s);
   }
-  if (crit == FF) return launch_one<FF, uint64_t>(a, wpb, lds_per_wave, grid, s);
-  if (crit == BF) return launch_one<BF, uint64_t>(a, wpb, lds_per_wave, grid, s);
-  return launch_one<WF, uint64_t>(a, wpb, lds_per_wave, grid, s);
+  if (crit == FF) return launch_sel<FF, uint64_t>(a, wpb, lds_per_wave, grid, s);
+  if (crit == BF) return launch_sel<BF, uint64_t>(a, wpb, lds_per_wave, grid, s);
+  return launch_sel<WF, uint64_t>(a, wpb, lds_per_wave, grid, s);
 }
 
 hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave,
@@ -362,15 +598,16 @@ hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int wpb, size_t
   return launch_plain_grid(a, crit, wide, wpb, lds_per_wave, 0, s);
 }
 
-int plain_blocks_per_cu(int crit, bool wide, int wpb, size_t lds_per_wave) {
+int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave) {
+  const bool ext = plain_ext(a), learned = a.type_rule == 2;
   if (!wide) {
-    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lds_per_wave);
-    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lds_per_wave);
-    return occupancy<WF, uint32_t>(wpb, lds_per_wave);
+    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lds_per_wave, ext, learned);
+    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lds_per_wave, ext, learned);
+    return occupancy<WF, uint32_t>(wpb, lds_per_wave, ext, learned);
   }
-  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lds_per_wave);
-  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lds_per_wave);
-  return occupancy<WF, uint64_t>(wpb, lds_per_wave);
+  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lds_per_wave, ext, learned);
+  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lds_per_wave, ext, learned);
+  return occupancy<WF, uint64_t>(wpb, lds_per_wave, ext, learned);
 }
 
 }  // namespace vsbpp

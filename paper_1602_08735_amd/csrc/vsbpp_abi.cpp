@@ -120,8 +120,11 @@ int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
   const bool wide = is_wide(a);
   sh->slots = round_up(a.max_items, 256);
   if (!wide && sh->slots > 65536) return VSBPP_E_SIZE;
-  sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide);
-  sh->max_wpb = (int)((size_t)device_info().max_lds_block / sh->per_wave);
+  const bool ext = plain_ext(a);
+  sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide, ext);
+  const size_t extra = ext ? plain_lds_block_extra(a.type_rule == 2) : 0;
+  if ((size_t)device_info().max_lds_block < extra + sh->per_wave) return VSBPP_E_SIZE;
+  sh->max_wpb = (int)(((size_t)device_info().max_lds_block - extra) / sh->per_wave);
   if (sh->max_wpb < 1) return VSBPP_E_SIZE;
   if (sh->max_wpb > 4) sh->max_wpb = 4;
   return VSBPP_OK;
@@ -238,7 +241,7 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     a.slots = sh.slots;
     const int wpb = c.wpb < sh.max_wpb ? c.wpb : sh.max_wpb;
     int grid = 0;
-    if (c.mode == 1) grid = d.cus * plain_blocks_per_cu(heuristic, wide, wpb, sh.per_wave);
+    if (c.mode == 1) grid = d.cus * plain_blocks_per_cu(a, heuristic, wide, wpb, sh.per_wave);
     e = launch_plain_grid(a, heuristic, wide, wpb, sh.per_wave, grid, s);
   } else {
     const int block = h_fit_block(heuristic, a, c.block);

@@ -1,0 +1,188 @@
+"""The learned bin-type scorer on the GPU against the CPU oracle: fused
+inference, decision features, forced rollouts and lookahead labels (bit for
+bit), lower bounds, training gradients and the gain of a trained scorer."""
+import numpy as np
+import pytest
+
+from paper_1602_08735_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+
+    import paper_1602_08735_amd as V
+
+    assert torch.cuda.is_available() and V.device_ok()
+    return V
+
+
+@pytest.fixture(scope="module")
+def L(V):
+    from paper_1602_08735_amd import learned
+
+    return learned
+
+
+def c2_batch(n, m, seed):
+    rng = np.random.default_rng(seed)
+    ws, cs = [], []
+    for _ in range(n):
+        w, c = inputs.c2_instance(rng, m)
+        ws.append(w)
+        cs.append(c)
+    return inputs.make_batch(ws, cs, None, np.arange(n, dtype=np.uint64))
+
+
+def to_oracle_model(orc, m):
+    om = orc.Model()
+    import ctypes
+
+    ctypes.memmove(ctypes.addressof(om), ctypes.addressof(m), ctypes.sizeof(orc.Model))
+    return om
+
+
+def device_model(V, m):
+    import ctypes
+
+    import torch
+
+    buf = torch.tensor(np.frombuffer(bytes(m), dtype=np.uint8).copy(), device="cuda")
+    return buf, buf.data_ptr()
+
+
+@pytest.mark.parametrize("h", ["FF", "BF", "WF"])
+def test_fused_inference_bit_exact(V, L, orc, h):
+    import torch
+
+    b = c2_batch(48, 300, 11)
+    db = V.DeviceBatch(b)
+    rng = np.random.default_rng(12)
+    for trial in range(3):
+        m = L.init_model(5, rng)
+        buf, ptr = device_model(V, m)
+        V.pack_batch_ex(db, h, model_ptr=ptr, type_rule=V.TYPE_LEARNED)
+        torch.cuda.synchronize()
+        a = db.assignment.cpu().numpy()
+        t = db.bin_types.cpu().numpy()
+        cost = db.cost.cpu().numpy()
+        om = to_oracle_model(orc, m)
+        for i in range(b.n_instances):
+            w, caps, _ = b.instance(i)
+            r = orc.pack(w, caps, h, type_rule=orc.TYPE_LEARNED, model=om)
+            lo, hi = int(b.item_off[i]), int(b.item_off[i + 1])
+            assert int(cost[i]) == r.cost, (trial, i)
+            assert np.array_equal(a[lo:hi], r.assignment), (trial, i)
+            assert np.array_equal(t[lo:lo + r.nbins], r.bin_types), (trial, i)
+
+
+def test_decision_features_bit_exact(V, L, orc):
+    b = c2_batch(20, 400, 13)
+    db = V.DeviceBatch(b)
+    rng = np.random.default_rng(14)
+    for crit in (0, 1, 2):
+        nd = L.plain_decisions(db, crit)
+        src, d = L.sample_decisions(nd, 15, rng)
+        x, info = L.decision_features(db, crit, src, d)
+        x, info = x.cpu().numpy(), info.cpu().numpy()
+        for e in range(len(src)):
+            w, caps, _ = b.instance(int(src[e]))
+            dec = orc.pack(w, caps, crit, trace=True).stats["decisions"][int(d[e])]
+            assert np.array_equal(x[e], np.array(dec.feat, np.float32)), (crit, e)
+            assert info[e, 0] == dec.feasible and info[e, 1] == dec.plain_type
+
+
+def test_rollouts_and_labels_bit_exact(V, L, orc):
+    b = c2_batch(16, 150, 15)
+    db = V.DeviceBatch(b)
+    rng = np.random.default_rng(16)
+    for crit in (0, 1, 2):
+        nd = L.plain_decisions(db, crit)
+        src, d = L.sample_decisions(nd, 6, rng)
+        _, info = L.decision_features(db, crit, src, d)
+        labels, vals = L.lookahead_labels(db, crit, src, d, info, 5, values=True)
+        labels, vals = labels.cpu().numpy(), vals.cpu().numpy().reshape(-1, 5)
+        for e in range(len(src)):
+            w, caps, _ = b.instance(int(src[e]))
+            lab, ov = orc.rollout_label(w, caps, crit, int(d[e]))
+            assert labels[e] == lab, (crit, e)
+            assert np.array_equal(vals[e], ov), (crit, e)
+
+
+def test_lower_bounds(V, orc):
+    import torch
+
+    rng = np.random.default_rng(17)
+    b = inputs.random_batch(rng, 120, 1, 400, b1_hi=3000)
+    db = V.DeviceBatch(b)
+    out = torch.empty(3 * b.n_instances, dtype=torch.int64, device="cuda")
+    V.lower_bounds(db, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().reshape(-1, 3)
+    for i in range(b.n_instances):
+        w, caps, _ = b.instance(i)
+        assert o[i, 0] == orc.lb_sum(w)
+        assert o[i, 1] == orc.lb_cap(w, caps), i
+        assert o[i, 2] == orc.lb_big(w, caps)
+
+
+def test_training_gradient_matches_float64(V, L):
+    import torch
+
+    from oracle import mlp_train
+
+    rng = np.random.default_rng(18)
+    n = 3000
+    X = rng.uniform(0, 1, (n, 16)).astype(np.float32)
+    mask = (rng.integers(0, 32, n) | 1).astype(np.int32)
+    label = np.array([int(rng.choice(np.flatnonzero((m >> np.arange(5)) & 1))) for m in mask],
+                     np.int32)
+    m0 = L.init_model(5, rng)
+    tr = V.Trainer(m0)
+    tx = torch.as_tensor(X, device="cuda")
+    tm = torch.as_tensor(mask, device="cuda")
+    tl = torch.as_tensor(label, device="cuda")
+    idx = rng.choice(n, 1000, replace=False).astype(np.int32)
+    g = tr.gradient(tx, tm, tl, torch.as_tensor(idx, device="cuda"))
+    a = L.model_arrays(m0)
+    flat = np.concatenate([a["w1"].ravel(), a["b1"], a["w2"].ravel(), a["b2"], a["w3"].ravel(),
+                           a["b3"]]).astype(np.float64)
+    _, ref = mlp_train.loss_and_grad(flat, 5, X[idx], mask[idx], label[idx])
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(g - ref)) <= 2e-4 * scale + 1e-7, np.max(np.abs(g - ref)) / scale
+    # training lowers the loss, deterministically
+    t1, l1 = L.train(tx, tm, tl, 5, epochs=6, batch=1000, lr=3e-3,
+                     rng=np.random.default_rng(1), init=m0)
+    t2, l2 = L.train(tx, tm, tl, 5, epochs=6, batch=1000, lr=3e-3,
+                     rng=np.random.default_rng(1), init=m0)
+    assert l1[-1] < l1[0]
+    assert bytes(t1.export()) == bytes(t2.export())
+
+
+def test_trained_scorer_gain(V, L):
+    """Labels from rollouts on training instances, GPU training, then paired
+    evaluation on held-out instances: reports mean cost/LB of the plain rule
+    and of the learned scorer (BF)."""
+    import torch
+
+    rng = np.random.default_rng(19)
+    tb = c2_batch(600, 500, 20)
+    tdb = V.DeviceBatch(tb)
+    nd = L.plain_decisions(tdb, 1)
+    src, d = L.sample_decisions(nd, 40, rng)
+    x, info = L.decision_features(tdb, 1, src, d)
+    labels = L.lookahead_labels(tdb, 1, src, d, info, 5)
+    mask = info[:, 0].contiguous()
+    tr, losses = L.train(x, mask, labels, 5, epochs=8, batch=2048, lr=3e-3, rng=rng)
+    eb = c2_batch(512, 500, 21)
+    edb = V.DeviceBatch(eb)
+    res = L.evaluate(edb, 1, tr.device_model)
+    plain = res["plain"]["cost_over_lb"].mean()
+    learned = res["learned"]["cost_over_lb"].mean()
+    print(f"BF plain cost/LB {plain:.5f}  learned {learned:.5f}  "
+          f"paired diff {res['paired_mean_diff']:.5f} CI {res['paired_ci95']}")
+    assert losses[-1] < losses[0]
+    assert np.all(res["learned"]["cost"] >= res["lb"])
+    assert learned < plain, (learned, plain)

@@ -188,3 +188,29 @@ def test_non_finite_scores_fall_back(orc):
     bad = _constant_model(orc, [1.0, np.inf, 0.0, 0.0, 0.0])
     r = orc.pack(w, caps, "BF", type_rule=orc.TYPE_LEARNED, model=bad)
     assert np.array_equal(r.assignment, orc.pack(w, caps, "BF").assignment)
+
+
+def test_training_gradient_finite_differences():
+    """The float64 training reference: analytic gradient = central finite
+    differences of its own loss (on parameters of every block)."""
+    from oracle import mlp_train
+
+    rng = np.random.default_rng(8)
+    n_out = 5
+    npar = 1024 + 64 + 4096 + 64 + 65 * n_out
+    flat = rng.normal(0, 0.3, npar)
+    X = rng.uniform(0, 1, (12, 16))
+    mask = rng.integers(1, 32, 12) | 1
+    label = np.array([int(rng.choice(np.flatnonzero((m >> np.arange(5)) & 1))) for m in mask])
+    loss, g = mlp_train.loss_and_grad(flat, n_out, X, mask, label)
+    assert np.isfinite(loss)
+    picks = np.concatenate([rng.integers(0, 1024, 6), 1024 + rng.integers(0, 64, 4),
+                            1088 + rng.integers(0, 4096, 6), 5184 + rng.integers(0, 64, 4),
+                            5248 + rng.integers(0, 320, 6), 5568 + np.arange(5)])
+    h = 1e-6
+    for p in picks:
+        e = np.zeros(npar)
+        e[p] = h
+        fd = (mlp_train.loss_only(flat + e, n_out, X, mask, label)
+              - mlp_train.loss_only(flat - e, n_out, X, mask, label)) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-6 + 1e-5 * abs(fd), (p, fd, g[p])
