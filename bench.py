@@ -4,12 +4,15 @@
 Workload: the uniform batch -- 4096 instances x 1000 items, 5 bin types with
 B_1 = 200 and four distinct capacities from [100,199], weights uniform in
 [1,200] (synthetic, seeded).  One step packs the whole batch, resident in
-HBM, with every heuristic of the path: plain First/Best/Worst Fit and the two
-hybrid-P-system heuristics (one launch each).  The value is items placed per
-second over the whole step (each heuristic places every item of the batch).
+HBM, with every packing kernel of the path: plain First/Best/Worst Fit, the
+two hybrid-P-system heuristics, and First/Best/Worst Fit with the learned
+bin-type scorer.  Every one runs as an autotuned plan replayed from a HIP
+graph (tuning and capture happen before the timed region).  The value is
+items placed per second over the whole step (every launch places every item
+of the batch).
 
-Prints one JSON line.  Per-kernel durations come from HIP events recorded
-around every launch on the launch stream during the timed region.
+Prints one JSON line.  Per-launch durations come from HIP events recorded
+around every graph replay on the launch stream during the timed region.
 """
 from __future__ import annotations
 
@@ -20,13 +23,17 @@ import sys
 import time
 
 HEURISTICS = ("FF", "BF", "WF", "H1", "H2")
+LEARNED = ("FF+scorer", "BF+scorer", "WF+scorer")
+MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1602_08735_amd",
+                         "models")
 
 # Algorithmic work per item on the uniform-batch distribution, from the
 # oracle's instrumented run (bin tests: open bins visited by the fit test;
 # for FF/BF/WF the live ones, i.e. room >= smallest weight still to come; for
 # the P-system packers every bin of the packer).  Re-measured by the
 # CPU-baseline leg on its own sample and reported next to these.
-BIN_TESTS_PER_ITEM = {"FF": 235.1, "BF": 232.8, "WF": 339.5, "H1": 6.2, "H2": 574.0}
+BIN_TESTS_PER_ITEM = {"FF": 235.1, "BF": 232.8, "WF": 339.5, "H1": 6.2, "H2": 574.0,
+                      "FF+scorer": 235.1, "BF+scorer": 232.8, "WF+scorer": 339.5}
 OPS_PER_BIN_TEST = 2          # form the room-after key, fold it into the min
 ALU_PEAK = 256 * 4 * 16 * 2.4e9   # int32 VALU lane-ops/s: CUs x SIMDs x lanes x clock
 
@@ -40,7 +47,9 @@ def parse():
     ap.add_argument("--items", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)
-    ap.add_argument("--heuristics", default=",".join(HEURISTICS))
+    ap.add_argument("--heuristics", default=",".join(HEURISTICS + LEARNED))
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy (outside the timed region) "
                          "as the known-size reference for HBM traffic counters")
@@ -84,6 +93,44 @@ def cpu_baseline(batch, heuristics, n_sample):
     }, per_item
 
 
+def best_of_orderings(V, torch, batch, crit, k, lb):
+    """The plain heuristic on k orderings of every instance (the input order
+    and k-1 seeded random permutations), best cost kept per instance: the
+    comparison for the learned scorer at equal instances/s."""
+    import numpy as np
+
+    from paper_1602_08735_amd import inputs
+
+    rng = np.random.default_rng(77)
+    sub = []
+    for o in range(k):
+        b = inputs.make_batch([batch.instance(i)[0] for i in range(batch.n_instances)],
+                              [batch.instance(i)[1] for i in range(batch.n_instances)],
+                              [np.arange(int(batch.item_off[i + 1] - batch.item_off[i]),
+                                         dtype=np.int32) if o == 0 else
+                               rng.permutation(int(batch.item_off[i + 1] - batch.item_off[i]))
+                               .astype(np.int32) for i in range(batch.n_instances)])
+        sub.append(b)
+    costs = []
+    ms = 0.0
+    for b in sub:
+        d = V.DeviceBatch(b)
+        p = V.Plan(d, crit)
+        p.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        costs.append(d.cost.cpu().numpy().astype(np.float64))
+        p.close()
+    best = np.min(np.stack(costs), axis=0)
+    return {"cost_over_lb": float((best / lb).mean()),
+            "instances_per_s": batch.n_instances / (ms / 1e3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -101,12 +148,34 @@ def main():
     batch = inputs.config2(n_instances=args.instances, m=args.items)
     db = V.DeviceBatch(batch)
     stream = torch.cuda.current_stream()
+    # one output set per launch so the learned and plain results stay apart
+    outs = {h: V.DeviceBatch.__new__(V.DeviceBatch) for h in heuristics}
+    for h in heuristics:
+        o = outs[h]
+        o.__dict__.update(db.__dict__)
+        o.assignment = torch.empty_like(db.assignment)
+        o.bin_types = torch.empty_like(db.bin_types)
+        o.nbins = torch.empty_like(db.nbins)
+        o.cost = torch.empty_like(db.cost)
+    models = {}
+    plans = {}
+    for h in heuristics:
+        if h.endswith("+scorer"):
+            crit = h.split("+")[0]
+            with open(os.path.join(MODEL_DIR, f"scorer_{crit}.bin"), "rb") as f:
+                raw = f.read()
+            models[h] = torch.tensor(np.frombuffer(raw, dtype=np.uint8).copy(), device="cuda")
+            plans[h] = V.Plan(outs[h], crit, type_rule=V.TYPE_LEARNED,
+                              model_ptr=models[h].data_ptr(), graph=not args.no_graph,
+                              autotune=not args.no_autotune)
+        else:
+            plans[h] = V.Plan(outs[h], h, graph=not args.no_graph, autotune=not args.no_autotune)
 
     def step(ev=None):
         for k, h in enumerate(heuristics):
             if ev is not None:
                 ev[k][0].record(stream)
-            V.pack_batch(db, h, stream=stream)
+            plans[h].run(stream)
             if ev is not None:
                 ev[k][1].record(stream)
 
@@ -137,18 +206,37 @@ def main():
     items = batch.total_items
     value = len(heuristics) * items / (ms_step / 1e3)
 
-    # outputs of every heuristic once more, for the quality figures
+    # quality of every launch's outputs, against the GPU lower bounds
+    lbt = torch.empty(3 * db.n, dtype=torch.int64, device="cuda")
+    V.lower_bounds(db, lbt)
+    torch.cuda.synchronize()
+    l3 = lbt.cpu().numpy().reshape(-1, 3)
+    lb = np.maximum(l3[:, 1], l3[:, 2]).astype(np.float64)
     quality = {}
     for h in heuristics:
-        V.pack_batch(db, h, stream=stream)
-        torch.cuda.synchronize()
-        nb = db.nbins.cpu().numpy()
+        nb = outs[h].nbins.cpu().numpy()
         if (nb < 0).any():
             raise RuntimeError(f"{h}: device reported instance errors")
-        cost = db.cost.cpu().numpy().astype(np.float64)
-        quality[h] = {"mean_cost": float(cost.mean()),
-                      "mean_utilisation": float((np.add.reduceat(
-                          batch.weights.astype(np.int64), batch.item_off[:-1]) / cost).mean())}
+        cost = outs[h].cost.cpu().numpy().astype(np.float64)
+        quality[h] = {"mean_cost_over_lb": float((cost / lb).mean()),
+                      "mean_utilisation": float((l3[:, 0] / cost).mean())}
+    learned_cmp = {}
+    for h in heuristics:
+        if not h.endswith("+scorer"):
+            continue
+        crit = h.split("+")[0]
+        if crit not in kern_ms:
+            continue
+        ratio = kern_ms[h] / kern_ms[crit]
+        kbest = max(1, int(np.ceil(ratio)))
+        best = best_of_orderings(V, torch, batch, crit, kbest, lb)
+        learned_cmp[crit] = {
+            "plain_cost_over_lb": quality[crit]["mean_cost_over_lb"],
+            "learned_cost_over_lb": quality[h]["mean_cost_over_lb"],
+            "plain_instances_per_s": args.instances / (kern_ms[crit] / 1e3),
+            "learned_instances_per_s": args.instances / (kern_ms[h] / 1e3),
+            "iso_throughput_plain_best_of_orderings": {"orderings": kbest, **best},
+        }
 
     per_kernel = {}
     for h in heuristics:
@@ -198,6 +286,8 @@ def main():
         "h2_permutation_placements_per_s": (120 * items / (kern_ms["H2"] / 1e3)
                                             if "H2" in kern_ms else None),
         "quality": quality,
+        "learned_vs_plain": learned_cmp,
+        "launch_shapes": {h: plans[h].launch() for h in heuristics},
     }
     if not args.no_cpu_baseline:
         cb, per_item = cpu_baseline(batch, heuristics, args.cpu_sample)

@@ -210,6 +210,13 @@ typedef struct vsbpp_plan vsbpp_plan;
  * Returns VSBPP_OK or a negative code; *out is NULL on error. */
 int32_t vsbpp_plan_create(const vsbpp_batch* batch, int32_t heuristic, const vsbpp_options* opt,
                           const vsbpp_launch* launch, uint32_t flags, vsbpp_plan** out);
+/* As vsbpp_plan_create with a scorer: opt->type_rule VSBPP_TYPE_LEARNED and
+ * d_model (a device pointer to a vsbpp_model, which must stay valid while
+ * the plan is used); plain FF/BF/WF only.  Declared with the scorer below. */
+struct vsbpp_model;
+int32_t vsbpp_plan_create_ex(const vsbpp_batch* batch, int32_t heuristic,
+                             const vsbpp_options* opt, const struct vsbpp_model* d_model,
+                             const vsbpp_launch* launch, uint32_t flags, vsbpp_plan** out);
 /* Enqueues one run on hip_stream (graph replay when captured). */
 int32_t vsbpp_plan_run(vsbpp_plan* plan, void* hip_stream);
 /* Launch shape the plan uses. */

@@ -255,8 +255,10 @@ static float bf16_to_f32(uint16_t h) {
 
 static float relu(float v) { return v > 0.0f ? v : 0.0f; }
 
-/* Every output is its bias followed by a chain of fused multiply-adds over
- * the inputs in index order, in fp32; hidden layers take ReLU. */
+/* Hidden outputs are their bias followed by a chain of fused multiply-adds
+ * over the inputs in index order (fp32), then ReLU.  An output score z[k] is
+ * its bias plus, in order g = 0..7, the partial sums p_g = fused
+ * multiply-add chain over inputs 8g..8g+7 started from 0. */
 void orc_mlp_forward(const orc_model* mdl, const float* x, float* z) {
   float h1[ORC_HIDDEN], h2[ORC_HIDDEN];
   for (int l = 0; l < ORC_HIDDEN; ++l) {
@@ -271,7 +273,12 @@ void orc_mlp_forward(const orc_model* mdl, const float* x, float* z) {
   }
   for (int k = 0; k < mdl->n_out; ++k) {
     float acc = mdl->b3[k];
-    for (int j = 0; j < ORC_HIDDEN; ++j) acc = fmaf(bf16_to_f32(mdl->w3[k * ORC_HIDDEN + j]), h2[j], acc);
+    for (int g = 0; g < 8; ++g) {
+      float p = 0.0f;
+      for (int r = 0; r < 8; ++r)
+        p = fmaf(bf16_to_f32(mdl->w3[k * ORC_HIDDEN + 8 * g + r]), h2[8 * g + r], p);
+      acc = acc + p;
+    }
     z[k] = acc;
   }
 }
@@ -294,28 +301,31 @@ static int32_t room_bucket(int64_t r, int32_t b1) {
   return (int32_t)(k > 5 ? 5 : k);
 }
 
-/* The 16 decision features (fp32):
- *  0  w / B_1
- *  1  items after this one / m
- *  2  mean weight of the items after this one / B_1 (0 if none)
- *  3  smallest weight after this one / B_1 (1 if none)
- *  4  bins opened so far / m
- *  5..10  share of the opened bins in each room bucket floor(6r/(B_1+1))
- *  11..14 B_2..B_5 / B_1 (0 beyond n)
- *  15 w / smallest capacity >= w */
+/* The 16 decision features (fp32; "* (1/a)" multiplies by the fp32
+ * reciprocal 1.0f/a):
+ *  0  w * (1/B_1)
+ *  1  (items after this one) * (1/m)
+ *  2  ((weight of the items after this one) / (their count)) * (1/B_1), 0 if none
+ *  3  (smallest weight after this one) * (1/B_1), 1 if none
+ *  4  (bins opened so far) * (1/m)
+ *  5..10  (bins so far in room bucket floor(6r/(B_1+1))) * (1/max(bins, 1))
+ *  11..14 B_2..B_5 * (1/B_1) (0 beyond n)
+ *  15 w * (1/(smallest capacity >= w)) */
 static void decision_features(const plain_ctx* c, float* x) {
-  const float b1 = (float)c->caps[0];
+  const float inv_b1 = 1.0f / (float)c->caps[0];
+  const float inv_m = 1.0f / (float)c->m;
   const int32_t rem = c->m - c->q - 1;
   const int64_t rsum = c->total - c->placed - c->w;
-  x[0] = (float)c->w / b1;
-  x[1] = (float)rem / (float)c->m;
-  x[2] = rem > 0 ? (float)rsum / (float)((int64_t)rem * (int64_t)c->caps[0]) : 0.0f;
-  x[3] = rem > 0 ? (float)c->smin_after / b1 : 1.0f;
-  x[4] = (float)c->nb / (float)c->m;
-  const float den = (float)(c->nb > 0 ? c->nb : 1);
-  for (int k = 0; k < 6; ++k) x[5 + k] = (float)c->hist[k] / den;
-  for (int k = 1; k <= 4; ++k) x[10 + k] = k < c->n ? (float)c->caps[k] / b1 : 0.0f;
-  x[15] = (float)c->w / (float)c->caps[open_type(c->caps, c->n, c->w, ORC_TYPE_SMALLEST_FIT)];
+  x[0] = (float)c->w * inv_b1;
+  x[1] = (float)rem * inv_m;
+  x[2] = rem > 0 ? ((float)rsum / (float)rem) * inv_b1 : 0.0f;
+  x[3] = rem > 0 ? (float)c->smin_after * inv_b1 : 1.0f;
+  x[4] = (float)c->nb * inv_m;
+  const float inv_den = 1.0f / (float)(c->nb > 0 ? c->nb : 1);
+  for (int k = 0; k < 6; ++k) x[5 + k] = (float)c->hist[k] * inv_den;
+  for (int k = 1; k <= 4; ++k) x[10 + k] = k < c->n ? (float)c->caps[k] * inv_b1 : 0.0f;
+  x[15] = (float)c->w *
+          (1.0f / (float)c->caps[open_type(c->caps, c->n, c->w, ORC_TYPE_SMALLEST_FIT)]);
 }
 
 static int32_t plain_choose(void* vc, int32_t w) {

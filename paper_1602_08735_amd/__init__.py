@@ -35,6 +35,7 @@ EXPORTS = (
     "vsbpp_pack_batch_ex", "vsbpp_rollout_labels", "vsbpp_trainer_create",
     "vsbpp_trainer_step", "vsbpp_trainer_gradient", "vsbpp_trainer_device_model",
     "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
+    "vsbpp_plan_create_ex",
 )
 
 
@@ -255,7 +256,7 @@ class Plan:
     def __init__(self, db: DeviceBatch, heuristic, *, launch: dict | None = None,
                  graph: bool = False, autotune: bool = False, seed: int = 0, s1: int = 10,
                  s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
-                 use_order: bool = True, use_seeds: bool = True):
+                 use_order: bool = True, use_seeds: bool = True, model_ptr=None):
         L = _plan_lib()
         ptr = lambda x: None if x is None else x.data_ptr()
         self.db = db
@@ -271,9 +272,17 @@ class Plan:
                         launch.get("waves_per_block", 4), launch.get("block_threads", 256))
         flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
         h = ctypes.c_void_p()
-        rc = L.vsbpp_plan_create(ctypes.byref(self._desc), _heur(heuristic), ctypes.byref(o),
-                                 ctypes.byref(lp) if lp is not None else None, flags,
-                                 ctypes.byref(h))
+        if model_ptr is not None:
+            L = _learn_lib()
+            rc = L.vsbpp_plan_create_ex(ctypes.byref(self._desc), _heur(heuristic),
+                                        ctypes.byref(o), model_ptr,
+                                        ctypes.byref(lp) if lp is not None else None, flags,
+                                        ctypes.byref(h))
+        else:
+            rc = L.vsbpp_plan_create(ctypes.byref(self._desc), _heur(heuristic),
+                                     ctypes.byref(o),
+                                     ctypes.byref(lp) if lp is not None else None, flags,
+                                     ctypes.byref(h))
         if rc != 0:
             raise VsbppError(rc, "vsbpp_plan_create")
         self._h = h
@@ -361,6 +370,10 @@ def _learn_lib():
         L.vsbpp_trainer_export.argtypes = [vp, ctypes.POINTER(Model)]
         L.vsbpp_trainer_destroy.restype = None
         L.vsbpp_trainer_destroy.argtypes = [vp]
+        L.vsbpp_plan_create_ex.restype = i32
+        L.vsbpp_plan_create_ex.argtypes = [ctypes.POINTER(_BatchDesc), i32, ctypes.POINTER(Options),
+                                           vp, ctypes.POINTER(Launch), ctypes.c_uint32,
+                                           ctypes.POINTER(vp)]
         L.vsbpp_lower_bounds.restype = i32
         L.vsbpp_lower_bounds.argtypes = [i32, vp, vp, vp, vp, vp, vp]
         L._learn_ready = True

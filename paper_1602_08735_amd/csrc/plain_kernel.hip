@@ -129,17 +129,19 @@ __device__ int compact(K* keys, typename KeyT<K>::Pid* pid, int nlive, int32_t T
 
 // ---------------------------------------------------------------------------
 // Learned bin-type scorer, evaluated by one wavefront: lane l computes hidden
-// unit l (and output l & 15); every output is its bias followed by an fp32
-// fused-multiply-add chain over its inputs in index order.  The model is
-// staged once per workgroup in LDS with 8 consecutive bf16 weights of one
-// output row per 16-byte word, rows of a column block adjacent, so the 64
-// lanes read unit-stride.
+// unit l of both hidden layers (bias, then an fp32 fused-multiply-add chain
+// over the inputs in index order, then ReLU).  The output layer runs on lanes
+// (k, g) = (lane >> 3, lane & 7): lane (k, g) forms the partial chain over
+// inputs 8g..8g+7 of output k, and lane k adds its bias and the eight
+// partials in order g = 0..7.  The model is staged once per workgroup in LDS
+// as fp32, laid out so the lanes of a wavefront read unit-stride 16-byte words.
 // ---------------------------------------------------------------------------
 struct ModelLds {
-  uint16_t w1[2 * 64 * 8];   // [i/8][l][8]
-  uint16_t w2[8 * 64 * 8];   // [j/8][l][8]
-  uint16_t w3[8 * 16 * 8];   // [j/8][k][8]
+  float w1[4 * 64 * 4];    // [i/4][l][4]
+  float w2[16 * 64 * 4];   // [j/4][l][4]
+  float w3[16 * 8 * 8];    // [k][g][8]
   float b1[64], b2[64], b3[16];
+  int32_t n_out;
 };
 
 __device__ __forceinline__ float bf16f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
@@ -147,65 +149,86 @@ __device__ __forceinline__ float bf16f(uint32_t bits16) { return __uint_as_float
 __device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
   for (int e = threadIdx.x; e < 64 * 16; e += blockDim.x) {
     const int l = e >> 4, i = e & 15;
-    s->w1[(((i >> 3) * 64) + l) * 8 + (i & 7)] = m->w1[e];
+    s->w1[(((i >> 2) * 64) + l) * 4 + (i & 3)] = bf16f(m->w1[e]);
   }
   for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
     const int l = e >> 6, j = e & 63;
-    s->w2[(((j >> 3) * 64) + l) * 8 + (j & 7)] = m->w2[e];
+    s->w2[(((j >> 2) * 64) + l) * 4 + (j & 3)] = bf16f(m->w2[e]);
   }
-  for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
-    const int k = e >> 6, j = e & 63;
-    s->w3[(((j >> 3) * 16) + k) * 8 + (j & 7)] = m->w3[e];
-  }
+  for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) s->w3[e] = bf16f(m->w3[e]);
   for (int e = threadIdx.x; e < 64; e += blockDim.x) {
     s->b1[e] = m->b1[e];
     s->b2[e] = m->b2[e];
     if (e < 16) s->b3[e] = m->b3[e];
   }
+  if (threadIdx.x == 0) {
+    const int n = m->n_out;
+    s->n_out = n < 1 ? 1 : (n > 16 ? 16 : n);
+  }
 }
 
-// z for this lane's output (lane & 15); x are wave-uniform features, hbuf a
-// 64-float LDS scratch of this wavefront.
+// Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
+// x: wave-uniform features; hbuf: 128 floats of LDS scratch of this wavefront.
 __device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], float* hbuf,
                                   int lane) {
   float acc = md->b1[lane];
 #pragma unroll
-  for (int ib = 0; ib < 2; ++ib) {
-    const uint4 wv = *reinterpret_cast<const uint4*>(&md->w1[(ib * 64 + lane) * 8]);
-    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      acc = __builtin_fmaf(bf16f((wr[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu), x[ib * 8 + r], acc);
+  for (int ib = 0; ib < 4; ++ib) {
+    const float4 wv = *reinterpret_cast<const float4*>(&md->w1[(ib * 64 + lane) * 4]);
+    acc = __builtin_fmaf(wv.x, x[ib * 4], acc);
+    acc = __builtin_fmaf(wv.y, x[ib * 4 + 1], acc);
+    acc = __builtin_fmaf(wv.z, x[ib * 4 + 2], acc);
+    acc = __builtin_fmaf(wv.w, x[ib * 4 + 3], acc);
   }
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
   acc = md->b2[lane];
 #pragma unroll
-  for (int jb = 0; jb < 8; ++jb) {
-    const uint4 wv = *reinterpret_cast<const uint4*>(&md->w2[(jb * 64 + lane) * 8]);
-    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
-    const float4 h0 = *reinterpret_cast<const float4*>(&hbuf[jb * 8]);
-    const float4 h1 = *reinterpret_cast<const float4*>(&hbuf[jb * 8 + 4]);
-    const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      acc = __builtin_fmaf(bf16f((wr[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu), hv[r], acc);
+  for (int jb = 0; jb < 16; ++jb) {
+    const float4 wv = *reinterpret_cast<const float4*>(&md->w2[(jb * 64 + lane) * 4]);
+    const float4 hv = *reinterpret_cast<const float4*>(&hbuf[jb * 4]);
+    acc = __builtin_fmaf(wv.x, hv.x, acc);
+    acc = __builtin_fmaf(wv.y, hv.y, acc);
+    acc = __builtin_fmaf(wv.z, hv.z, acc);
+    acc = __builtin_fmaf(wv.w, hv.w, acc);
   }
-  const float h2 = acc > 0.0f ? acc : 0.0f;
-  hbuf[lane] = h2;
-  const int k = lane & 15;
-  acc = md->b3[k];
-#pragma unroll
-  for (int jb = 0; jb < 8; ++jb) {
-    const uint4 wv = *reinterpret_cast<const uint4*>(&md->w3[(jb * 16 + k) * 8]);
-    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
-    const float4 h0 = *reinterpret_cast<const float4*>(&hbuf[jb * 8]);
-    const float4 h1 = *reinterpret_cast<const float4*>(&hbuf[jb * 8 + 4]);
-    const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      acc = __builtin_fmaf(bf16f((wr[r >> 1] >> ((r & 1) * 16)) & 0xFFFFu), hv[r], acc);
+  hbuf[lane] = acc > 0.0f ? acc : 0.0f;
+  float* part = hbuf + 64;
+  const int g = lane & 7;
+  float z = 0.0f;
+  for (int kb = 0; kb < md->n_out; kb += 8) {
+    const int k = kb + (lane >> 3);
+    const float4 w0 = *reinterpret_cast<const float4*>(&md->w3[(k * 8 + g) * 8]);
+    const float4 w1 = *reinterpret_cast<const float4*>(&md->w3[(k * 8 + g) * 8 + 4]);
+    const float4 h0 = *reinterpret_cast<const float4*>(&hbuf[g * 8]);
+    const float4 h1 = *reinterpret_cast<const float4*>(&hbuf[g * 8 + 4]);
+    float p = 0.0f;
+    p = __builtin_fmaf(w0.x, h0.x, p);
+    p = __builtin_fmaf(w0.y, h0.y, p);
+    p = __builtin_fmaf(w0.z, h0.z, p);
+    p = __builtin_fmaf(w0.w, h0.w, p);
+    p = __builtin_fmaf(w1.x, h1.x, p);
+    p = __builtin_fmaf(w1.y, h1.y, p);
+    p = __builtin_fmaf(w1.z, h1.z, p);
+    p = __builtin_fmaf(w1.w, h1.w, p);
+    part[lane] = p;
+    // lane kb + t (t < 8) folds the partials of output kb + t in order
+    const int t = lane - kb;
+    if (t >= 0 && t < 8) {
+      const float4 p0 = *reinterpret_cast<const float4*>(&part[t * 8]);
+      const float4 p1 = *reinterpret_cast<const float4*>(&part[t * 8 + 4]);
+      float a = md->b3[lane];
+      a = a + p0.x;
+      a = a + p0.y;
+      a = a + p0.z;
+      a = a + p0.w;
+      a = a + p1.x;
+      a = a + p1.y;
+      a = a + p1.z;
+      a = a + p1.w;
+      z = a;
+    }
   }
-  return acc;
+  return z;
 }
 
 // inclusive suffix minimum over lanes [lane, 63]
@@ -446,29 +469,31 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
               const int64_t rsum = total - placed - w;
               int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
               after = min(after, next_min);
-              const float fb1 = (float)B1;
+              const float inv_b1 = 1.0f / (float)B1;
+              const float inv_m = 1.0f / (float)m;
               float x[16];
-              x[0] = (float)w / fb1;
-              x[1] = (float)rem / (float)m;
-              x[2] = rem > 0 ? (float)rsum / (float)((int64_t)rem * (int64_t)B1) : 0.0f;
-              x[3] = rem > 0 ? (float)after / fb1 : 1.0f;
-              x[4] = (float)nb / (float)m;
-              const float den = (float)(nb > 0 ? nb : 1);
+              x[0] = (float)w * inv_b1;
+              x[1] = (float)rem * inv_m;
+              x[2] = rem > 0 ? ((float)rsum / (float)rem) * inv_b1 : 0.0f;
+              x[3] = rem > 0 ? (float)after * inv_b1 : 1.0f;
+              x[4] = (float)nb * inv_m;
+              const float inv_den = 1.0f / (float)(nb > 0 ? nb : 1);
               const int4 h03 = *reinterpret_cast<const int4*>(hist);
               const int4 h47 = *reinterpret_cast<const int4*>(hist + 4);
-              x[5] = (float)h03.x / den;
-              x[6] = (float)h03.y / den;
-              x[7] = (float)h03.z / den;
-              x[8] = (float)h03.w / den;
-              x[9] = (float)h47.x / den;
-              x[10] = (float)h47.y / den;
+              x[5] = (float)h03.x * inv_den;
+              x[6] = (float)h03.y * inv_den;
+              x[7] = (float)h03.z * inv_den;
+              x[8] = (float)h03.w * inv_den;
+              x[9] = (float)h47.x * inv_den;
+              x[10] = (float)h47.y * inv_den;
 #pragma unroll
               for (int k = 1; k <= 4; ++k)
-                x[10 + k] = k < n ? (float)readlane(cap_lane, k) / fb1 : 0.0f;
-              x[15] = (float)w / (float)readlane(cap_lane, smallest);
-              if (a.type_rule == 2) {
+                x[10 + k] = k < n ? (float)readlane(cap_lane, k) * inv_b1 : 0.0f;
+              x[15] = (float)w * (1.0f / (float)readlane(cap_lane, smallest));
+              // with one type holding the item the scorer has nothing to choose
+              if (a.type_rule == 2 && smallest > 0) {
                 const float z = mlp_forward_wave(md, x, hbuf, lane);
-                const int kmax = min(n, (int)a.model->n_out);
+                const int kmax = min(n, md->n_out);
                 float zb = __uint_as_float(readlane(__float_as_uint(z), 0));
                 bool fin = __builtin_isfinite(zb);
                 int bi = 0;
@@ -572,7 +597,7 @@ size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext) {
   size_t b = (size_t)slots * ks;
   b += ((size_t)slots * ps + 15) & ~(size_t)15;
   b += (nch * 4 + 15) & ~(size_t)15;
-  if (ext) b += 16 * 4 + 64 * 4;  // room histogram + hidden-layer scratch
+  if (ext) b += 16 * 4 + 128 * 4;  // room histogram + hidden-layer scratch
   return b;
 }
 

@@ -46,7 +46,8 @@ int bucket(long long x) {
 
 std::string tune_key(int heuristic, const vsbpp::BatchArgs& a) {
   std::ostringstream k;
-  k << "h" << heuristic << "-m" << bucket(a.max_items) << "-t" << a.max_types << "-c"
+  k << "h" << heuristic << (a.type_rule == 2 ? "L" : "") << "-m" << bucket(a.max_items)
+    << "-t" << a.max_types << "-c"
     << (a.max_cap > 0x7FFF ? 1 : 0) << "-n" << bucket(a.num) << "-s"
     << (heuristic == VSBPP_H1 ? a.s1 : heuristic == VSBPP_H2 ? a.s2 : 0);
   return k.str();
@@ -159,6 +160,12 @@ extern "C" {
 
 int32_t vsbpp_plan_create(const vsbpp_batch* b, int32_t heuristic, const vsbpp_options* opt,
                           const vsbpp_launch* launch, uint32_t flags, vsbpp_plan** out) {
+  return vsbpp_plan_create_ex(b, heuristic, opt, nullptr, launch, flags, out);
+}
+
+int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp_options* opt,
+                             const vsbpp_model* d_model, const vsbpp_launch* launch,
+                             uint32_t flags, vsbpp_plan** out) {
   if (!out) return VSBPP_E_NULL;
   *out = nullptr;
   if (!b) return VSBPP_E_NULL;
@@ -170,9 +177,16 @@ int32_t vsbpp_plan_create(const vsbpp_batch* b, int32_t heuristic, const vsbpp_o
       b->max_capacity < 1)
     return VSBPP_E_SIZE;
   if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
-  const vsbpp_options o = vsbpp::resolve_options(opt);
+  vsbpp_options o = vsbpp::resolve_options(opt);
+  const bool learned = o.type_rule == VSBPP_TYPE_LEARNED;
+  if (learned) {
+    if (!d_model) return VSBPP_E_NULL;
+    if (heuristic > VSBPP_WF) return VSBPP_E_OPTION;
+    o.type_rule = VSBPP_TYPE_SMALLEST_FIT;  // shared checks below
+  }
   int32_t rc = vsbpp::check_options_public(o);
   if (rc != VSBPP_OK) return rc;
+  if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
 
   vsbpp_plan* p = new vsbpp_plan;
@@ -196,6 +210,7 @@ int32_t vsbpp_plan_create(const vsbpp_batch* b, int32_t heuristic, const vsbpp_o
   a.force_crit = o.force_criterion;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
+  a.model = learned ? d_model : nullptr;
   p->heuristic = heuristic;
 
   if (hipMalloc(&p->workspace, sizeof(int32_t) * ((size_t)a.num + 1)) != hipSuccess) {

@@ -186,3 +186,34 @@ def test_trained_scorer_gain(V, L):
     assert losses[-1] < losses[0]
     assert np.all(res["learned"]["cost"] >= res["lb"])
     assert learned < plain, (learned, plain)
+
+
+def test_learned_plan_graph_replays(V, L, orc):
+    """A graph-captured, autotuned plan with the scorer, replayed with other
+    work in between, matches the oracle every time."""
+    import torch
+
+    b = c2_batch(64, 400, 23)
+    db = V.DeviceBatch(b)
+    m = L.init_model(5, np.random.default_rng(24))
+    buf, ptr = device_model(V, m)
+    om = to_oracle_model(orc, m)
+    exp = []
+    for i in range(b.n_instances):
+        w, caps, _ = b.instance(i)
+        exp.append(orc.pack(w, caps, "BF", type_rule=orc.TYPE_LEARNED, model=om))
+    p = V.Plan(db, "BF", type_rule=V.TYPE_LEARNED, model_ptr=ptr, graph=True, autotune=True)
+    for rep in range(3):
+        db.assignment.fill_(-1)
+        db.cost.fill_(0)
+        torch.cuda.synchronize()
+        p.run()
+        other = V.DeviceBatch(b)
+        V.pack_batch(other, "FF")
+        torch.cuda.synchronize()
+        a = db.assignment.cpu().numpy()
+        c = db.cost.cpu().numpy()
+        for i, r in enumerate(exp):
+            lo, hi = int(b.item_off[i]), int(b.item_off[i + 1])
+            assert int(c[i]) == r.cost and np.array_equal(a[lo:hi], r.assignment), (rep, i)
+    p.close()

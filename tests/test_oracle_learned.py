@@ -96,25 +96,27 @@ def test_decision_features_recount(orc):
                 q = e.position
                 x = np.array(e.feat, dtype=np.float32)
                 assert e.weight == w[q]
-                assert x[0] == np.float32(w[q]) / np.float32(b1)
-                assert x[1] == np.float32(m - q - 1) / np.float32(m)
+                f32 = np.float32
+                inv_b1, inv_m = f32(1) / f32(b1), f32(1) / f32(m)
+                assert x[0] == f32(w[q]) * inv_b1
+                assert x[1] == f32(m - q - 1) * inv_m
                 rem = w[q + 1:].astype(np.int64)
                 if rem.size:
-                    assert x[2] == np.float32(rem.sum()) / np.float32(rem.size * b1)
-                    assert x[3] == np.float32(rem.min()) / np.float32(b1)
+                    assert x[2] == (f32(rem.sum()) / f32(rem.size)) * inv_b1
+                    assert x[3] == f32(rem.min()) * inv_b1
                 else:
                     assert x[2] == 0.0 and x[3] == 1.0
-                assert x[4] == np.float32(d) / np.float32(m)
+                assert x[4] == f32(d) * inv_m
                 load = np.bincount(r.assignment[:q], weights=w[:q], minlength=d)[:d]
                 room = caps[r.bin_types[:d]].astype(np.int64) - load.astype(np.int64)
                 hist = np.bincount(np.minimum(5, 6 * room // (b1 + 1)), minlength=6)
-                den = np.float32(max(d, 1))
-                assert np.array_equal(x[5:11], hist.astype(np.float32) / den)
+                inv_den = f32(1) / f32(max(d, 1))
+                assert np.array_equal(x[5:11], hist.astype(f32) * inv_den)
                 for k in range(1, 5):
-                    exp = np.float32(caps[k]) / np.float32(b1) if k < caps.size else 0.0
+                    exp = f32(caps[k]) * inv_b1 if k < caps.size else 0.0
                     assert x[10 + k] == exp
                 sf = max(k for k in range(caps.size) if caps[k] >= w[q])
-                assert x[15] == np.float32(w[q]) / np.float32(caps[sf])
+                assert x[15] == f32(w[q]) * (f32(1) / f32(caps[sf]))
                 assert e.plain_type == sf and e.chosen == sf
                 assert e.feasible == sum(1 << k for k in range(caps.size) if caps[k] >= w[q])
 
