@@ -133,63 +133,77 @@ __device__ int compact(K* keys, typename KeyT<K>::Pid* pid, int nlive, int32_t T
 // over the inputs in index order, then ReLU).  The output layer runs on lanes
 // (k, g) = (lane >> 3, lane & 7): lane (k, g) forms the partial chain over
 // inputs 8g..8g+7 of output k, and lane k adds its bias and the eight
-// partials in order g = 0..7.  The model is staged once per workgroup in LDS
-// as fp32, laid out so the lanes of a wavefront read unit-stride 16-byte words.
+// partials in order g = 0..7.
+//
+// Row l of W1 and W2 (and b1[l], b2[l]) stays in lane l's registers for the
+// wavefront's lifetime, so a decision reads no hidden-layer weight from
+// memory; only the activations go through LDS (16-byte broadcasts).  The
+// output layer, which needs up to 16 outputs, is staged per workgroup in LDS.
 // ---------------------------------------------------------------------------
 struct ModelLds {
-  float w1[4 * 64 * 4];    // [i/4][l][4]
-  float w2[16 * 64 * 4];   // [j/4][l][4]
   float w3[16 * 8 * 8];    // [k][g][8]
-  float b1[64], b2[64], b3[16];
+  float b3[16];
   int32_t n_out;
+};
+
+constexpr size_t kModelLdsBytes = (sizeof(ModelLds) + 15) & ~(size_t)15;
+
+struct ScorerRegs {
+  float w1[16];
+  float w2[64];
+  float b1, b2;
 };
 
 __device__ __forceinline__ float bf16f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
 __device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
-  for (int e = threadIdx.x; e < 64 * 16; e += blockDim.x) {
-    const int l = e >> 4, i = e & 15;
-    s->w1[(((i >> 2) * 64) + l) * 4 + (i & 3)] = bf16f(m->w1[e]);
-  }
-  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-    const int l = e >> 6, j = e & 63;
-    s->w2[(((j >> 2) * 64) + l) * 4 + (j & 3)] = bf16f(m->w2[e]);
-  }
   for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) s->w3[e] = bf16f(m->w3[e]);
-  for (int e = threadIdx.x; e < 64; e += blockDim.x) {
-    s->b1[e] = m->b1[e];
-    s->b2[e] = m->b2[e];
-    if (e < 16) s->b3[e] = m->b3[e];
-  }
+  for (int e = threadIdx.x; e < 16; e += blockDim.x) s->b3[e] = m->b3[e];
   if (threadIdx.x == 0) {
     const int n = m->n_out;
     s->n_out = n < 1 ? 1 : (n > 16 ? 16 : n);
   }
 }
 
+__device__ void load_scorer_regs(const vsbpp_model* m, int lane, ScorerRegs& r) {
+  // rows start 4-byte aligned: two bf16 weights per load
+  const uint32_t* r1 = reinterpret_cast<const uint32_t*>(&m->w1[lane * 16]);
+  const uint32_t* r2 = reinterpret_cast<const uint32_t*>(&m->w2[lane * 64]);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t v = r1[i];
+    r.w1[2 * i] = bf16f(v & 0xFFFFu);
+    r.w1[2 * i + 1] = __uint_as_float(v & 0xFFFF0000u);
+  }
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const uint32_t v = r2[j];
+    r.w2[2 * j] = bf16f(v & 0xFFFFu);
+    r.w2[2 * j + 1] = __uint_as_float(v & 0xFFFF0000u);
+  }
+  r.b1 = m->b1[lane];
+  r.b2 = m->b2[lane];
+}
+
 // Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
 // x: wave-uniform features; hbuf: 128 floats of LDS scratch of this wavefront.
-__device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], float* hbuf,
-                                  int lane) {
-  float acc = md->b1[lane];
+__device__ float mlp_forward_wave(const ModelLds* md, const ScorerRegs& r, const float (&x)[16],
+                                  float* hbuf, int lane) {
+  float acc = r.b1;
 #pragma unroll
-  for (int ib = 0; ib < 4; ++ib) {
-    const float4 wv = *reinterpret_cast<const float4*>(&md->w1[(ib * 64 + lane) * 4]);
-    acc = __builtin_fmaf(wv.x, x[ib * 4], acc);
-    acc = __builtin_fmaf(wv.y, x[ib * 4 + 1], acc);
-    acc = __builtin_fmaf(wv.z, x[ib * 4 + 2], acc);
-    acc = __builtin_fmaf(wv.w, x[ib * 4 + 3], acc);
-  }
+  for (int i = 0; i < 16; ++i) acc = __builtin_fmaf(r.w1[i], x[i], acc);
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
-  acc = md->b2[lane];
+  acc = r.b2;
+  // all sixteen broadcasts are issued before the chain: one LDS round trip
+  float4 hv[16];
+#pragma unroll
+  for (int jb = 0; jb < 16; ++jb) hv[jb] = *reinterpret_cast<const float4*>(&hbuf[jb * 4]);
 #pragma unroll
   for (int jb = 0; jb < 16; ++jb) {
-    const float4 wv = *reinterpret_cast<const float4*>(&md->w2[(jb * 64 + lane) * 4]);
-    const float4 hv = *reinterpret_cast<const float4*>(&hbuf[jb * 4]);
-    acc = __builtin_fmaf(wv.x, hv.x, acc);
-    acc = __builtin_fmaf(wv.y, hv.y, acc);
-    acc = __builtin_fmaf(wv.z, hv.z, acc);
-    acc = __builtin_fmaf(wv.w, hv.w, acc);
+    acc = __builtin_fmaf(r.w2[jb * 4], hv[jb].x, acc);
+    acc = __builtin_fmaf(r.w2[jb * 4 + 1], hv[jb].y, acc);
+    acc = __builtin_fmaf(r.w2[jb * 4 + 2], hv[jb].z, acc);
+    acc = __builtin_fmaf(r.w2[jb * 4 + 3], hv[jb].w, acc);
   }
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
   float* part = hbuf + 64;
@@ -231,6 +245,19 @@ __device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], floa
   return z;
 }
 
+// Largest of the floats in lanes 0..15 (none NaN), as seen by lane 0: the
+// reduction runs on an order-preserving integer image of the values.
+__device__ __forceinline__ float row0_max(float f) {
+  const uint32_t b = __float_as_uint(f);
+  uint32_t v = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  v = max(v, dpp<kQuadSwap1>(0u, v));
+  v = max(v, dpp<kQuadSwap2>(0u, v));
+  v = max(v, dpp<kRowHalfMirror>(0u, v));
+  v = max(v, dpp<kRowMirror>(0u, v));
+  v = readlane(v, 0);
+  return __uint_as_float((v & 0x80000000u) ? (v & 0x7FFFFFFFu) : ~v);
+}
+
 // inclusive suffix minimum over lanes [lane, 63]
 __device__ __forceinline__ int32_t wave_suffix_min(int32_t v, int lane) {
 #pragma unroll
@@ -254,7 +281,11 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
   const int wave = uniform((int)(threadIdx.x >> 6));
-  unsigned char* base = smem + (size_t)wave * lds_per_wave;
+  // the scorer's weights sit at the start of LDS: every weight read is then
+  // one aligned 16-byte word at an immediate offset from the lane's base
+  ModelLds* md = reinterpret_cast<ModelLds*>(smem);
+  const size_t model_bytes = (EXT && a.type_rule == 2) ? kModelLdsBytes : 0;
+  unsigned char* base = smem + model_bytes + (size_t)wave * lds_per_wave;
   K* keys = reinterpret_cast<K*>(base);
   const size_t pid_bytes = ((size_t)a.slots * sizeof(Pid) + 15) & ~(size_t)15;
   Pid* pid = reinterpret_cast<Pid*>(base + (size_t)a.slots * sizeof(K));
@@ -262,10 +293,11 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   const size_t smin_bytes = (((size_t)a.max_items + 63) / 64 * 4 + 15) & ~(size_t)15;
   int32_t* hist = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(smin) + smin_bytes);
   float* hbuf = reinterpret_cast<float*>(hist + 16);
-  ModelLds* md = reinterpret_cast<ModelLds*>(smem + (size_t)wpb * lds_per_wave);
+  ScorerRegs sr{};
   if constexpr (EXT) {
     if (a.type_rule == 2) {
       stage_model(a.model, md);
+      load_scorer_regs(a.model, lane, sr);
       __syncthreads();
     }
   }
@@ -366,6 +398,11 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
     int32_t tprev = 0;
     int64_t cost = 0;
     int32_t typebuf = 0;
+    // First Fit: upper bound on the room of every bin in the scan array; an
+    // item heavier than it fits nowhere, so its scan is skipped (rooms only
+    // shrink, a new bin raises the bound, and a scan that finds no fit sets it
+    // to the largest room exactly)
+    int64_t ub = 0;
     for (int c = 0; c < nch; ++c) {
       const int32_t T = uniform(smin[c]);
       if (nlive > 0 && (dead > 0 || T > tprev)) {
@@ -394,11 +431,12 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
         const K wk = (K)w << KT::SH;
         int p = -1;
         K nk = 0;
-        const int ng = uniform((nlive + 255) >> 8);
+        const int ng = (CRIT == FF && (int64_t)w > ub) ? 0 : uniform((nlive + 255) >> 8);
         if constexpr (CRIT == FF) {
           // groups in position order; the next group's keys are loaded while
           // the four 64-bin rows of the current one are tested
           K k[4], kn[4];
+          K kmax = 0;
           if (ng > 0) load_group(keys, 0, lane, k);
           for (int g = 0; g < ng; ++g) {
             if (g + 1 < ng) load_group(keys, g + 1, lane, kn);
@@ -413,9 +451,11 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
               nk = readlane(kj, l) - wk;
               break;
             }
+            kmax = max(max(kmax, max(k[0], k[1])), max(k[2], k[3]));
 #pragma unroll
             for (int j = 0; j < 4; ++j) k[j] = kn[j];
           }
+          if (p < 0 && ng > 0) ub = (int64_t)(~wave_min(~kmax) >> KT::SH);
         } else {
           K best = ~(K)0;
           int g = 0;
@@ -492,21 +532,16 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
               x[15] = (float)w * (1.0f / (float)readlane(cap_lane, smallest));
               // with one type holding the item the scorer has nothing to choose
               if (a.type_rule == 2 && smallest > 0) {
-                const float z = mlp_forward_wave(md, x, hbuf, lane);
+                const float z = mlp_forward_wave(md, sr, x, hbuf, lane);
                 const int kmax = min(n, md->n_out);
-                float zb = __uint_as_float(readlane(__float_as_uint(z), 0));
-                bool fin = __builtin_isfinite(zb);
-                int bi = 0;
-                for (int k = 1; k < kmax; ++k) {
-                  const float zk = __uint_as_float(readlane(__float_as_uint(z), k));
-                  fin = fin && __builtin_isfinite(zk);
-                  if (((fm >> k) & 1ull) && zk > zb) {
-                    zb = zk;
-                    bi = k;
-                  }
-                }
+                // lanes 0..kmax-1 hold the scores; the choice is the lowest
+                // feasible type whose score equals the largest feasible score
+                const bool in = lane < kmax;
+                const bool feas = in && ((fm >> lane) & 1ull);
+                const float mx = row0_max(feas ? z : -__builtin_inff());
+                const int bi = (int)__builtin_ctzll(ballot(feas && z == mx));
                 // the scorer only proposes: non-finite scores fall back
-                t = fin ? bi : smallest;
+                t = ballot(in && !__builtin_isfinite(z)) == 0ull ? bi : smallest;
               }
               if (dump) {
                 if (a.feat_out && lane < 16) {
@@ -526,6 +561,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
           }
           const int32_t Bt = readlane(cap_lane, t);
           const K room = (K)(Bt - w);
+          if constexpr (CRIT == FF) ub = max(ub, (int64_t)room);
           p = nlive;
           nlive = uniform(nlive + 1);
           const int id = nb;
@@ -601,9 +637,7 @@ size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext) {
   return b;
 }
 
-size_t plain_lds_block_extra(bool learned) {
-  return learned ? ((sizeof(ModelLds) + 15) & ~(size_t)15) : 0;
-}
+size_t plain_lds_block_extra(bool learned) { return learned ? kModelLdsBytes : 0; }
 
 hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
                              size_t lds_per_wave, int grid, hipStream_t s) {
