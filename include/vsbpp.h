@@ -244,11 +244,18 @@ void vsbpp_plan_destroy(vsbpp_plan* plan);
 /*          floor(6 r / (B_1 + 1)) = 0..5                                     */
 /*   11..14 B_2 .. B_5 over B_1 (0 beyond n)                                  */
 /*   15 w / (smallest capacity >= w)                                          */
+/* Arithmetic: integers convert to fp32 first; "a / b" with b one of B_1, m, */
+/* the bins opened so far (at least 1) or a capacity is a * (1.0f / b), the */
+/* product with the fp32 reciprocal; the mean in feature 2 is the fp32      */
+/* quotient (sum / count), then times 1/B_1.                                */
 /* Network: h1 = relu(W1 x + b1) (64), h2 = relu(W2 h1 + b2) (64),           */
-/* z = W3 h2 + b3 (n_out); every output is its bias followed by a chain of   */
-/* fp32 fused multiply-adds over the inputs in index order, so results are   */
+/* z = W3 h2 + b3 (n_out).  A hidden unit is its bias followed by a chain of */
+/* fp32 fused multiply-adds over its inputs in index order.  Output k is     */
+/* b3[k] + p_0 + ... + p_7 (fp32 additions in that order), where p_g is a    */
+/* fused multiply-add chain from 0 over inputs 8g..8g+7.  So results are     */
 /* reproducible bit for bit.  Decision: the type k < min(n, n_out) holding   */
-/* the item with the largest z, lowest k on ties.                            */
+/* the item with the largest z, lowest k on ties; decisions where only B_1   */
+/* holds the item are not scored.                                            */
 /* ------------------------------------------------------------------------ */
 
 #define VSBPP_NFEAT 16
