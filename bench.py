@@ -30,12 +30,23 @@ MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1602
 # Algorithmic work per item on the uniform-batch distribution, from the
 # oracle's instrumented run (bin tests: open bins visited by the fit test;
 # for FF/BF/WF the live ones, i.e. room >= smallest weight still to come; for
-# the P-system packers every bin of the packer).  Re-measured by the
+# the P-system packers every bin of the packer).  The scorer runs pack
+# differently from the plain ones, so their bin tests are their own, and each
+# scored decision (an item that fits no open bin and more than one type
+# holds) costs one pass of the 16-64-64-5 network.  Re-measured by the
 # CPU-baseline leg on its own sample and reported next to these.
 BIN_TESTS_PER_ITEM = {"FF": 235.1, "BF": 232.8, "WF": 339.5, "H1": 6.2, "H2": 574.0,
-                      "FF+scorer": 235.1, "BF+scorer": 232.8, "WF+scorer": 339.5}
+                      "FF+scorer": 194.9, "BF+scorer": 184.5, "WF+scorer": 290.3}
+SCORED_DECISIONS_PER_ITEM = {"FF+scorer": 0.4851, "BF+scorer": 0.4799, "WF+scorer": 0.5401}
 OPS_PER_BIN_TEST = 2          # form the room-after key, fold it into the min
-ALU_PEAK = 256 * 4 * 16 * 2.4e9   # int32 VALU lane-ops/s: CUs x SIMDs x lanes x clock
+MLP_FMA_PER_DECISION = 16 * 64 + 64 * 64 + 64 * 5   # fused multiply-adds, one lane-op each
+ALU_PEAK = 256 * 4 * 16 * 2.4e9   # VALU lane-ops/s: CUs x SIMDs x lanes x clock
+
+
+def ops_per_item(h):
+    """Algorithmic VALU lane-ops per item placed by launch h."""
+    return (OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[h]
+            + MLP_FMA_PER_DECISION * SCORED_DECISIONS_PER_ITEM.get(h, 0.0))
 
 
 def parse():
@@ -67,12 +78,24 @@ def cpu_baseline(batch, heuristics, n_sample):
     idx = list(range(min(n_sample, batch.n_instances)))
     cores = max(1, min(16, os.cpu_count() or 1))
     counts = {h: [0, 0] for h in heuristics}
+    models = {}
+    for h in heuristics:
+        if h.endswith("+scorer"):
+            with open(os.path.join(MODEL_DIR, f"scorer_{h.split('+')[0]}.bin"), "rb") as f:
+                models[h] = oracle.Model.from_buffer_copy(f.read())
+
+    def run(h, i, trace=False):
+        w, caps, _ = batch.instance(i)
+        if h in models:
+            return oracle.pack(w, caps, h.split("+")[0], seed=int(batch.seeds[i]),
+                               type_rule=oracle.TYPE_LEARNED, model=models[h], trace=trace), w
+        return oracle.pack(w, caps, h, seed=int(batch.seeds[i])), w
 
     def one(args):
         h, i = args
-        w, caps, _ = batch.instance(i)
-        r = oracle.pack(w, caps, h, seed=int(batch.seeds[i]))
-        return h, r.stats["live_tests"] if h in ("FF", "BF", "WF") else r.stats["bin_tests"], w.size
+        r, w = run(h, i)
+        plain = h.split("+")[0] in ("FF", "BF", "WF")
+        return h, r.stats["live_tests"] if plain else r.stats["bin_tests"], w.size
 
     jobs = [(h, i) for h in heuristics for i in idx]
     t0 = time.perf_counter()
@@ -83,6 +106,15 @@ def cpu_baseline(batch, heuristics, n_sample):
     dt = time.perf_counter() - t0
     items = sum(c[1] for c in counts.values())
     per_item = {h: round(c[0] / max(c[1], 1), 1) for h, c in counts.items()}
+    # scored decisions per item of the scorer runs, on a small untimed sample
+    scored = {}
+    for h in models:
+        sd = it = 0
+        for i in idx[:64]:
+            r, w = run(h, i, trace=True)
+            sd += sum(1 for e in r.stats["decisions"] if e.feasible & ~1)
+            it += w.size
+        scored[h] = round(sd / max(it, 1), 4)
     return {
         "value": items / dt,
         "unit": "items/s",
@@ -90,7 +122,7 @@ def cpu_baseline(batch, heuristics, n_sample):
         "kind": "oracle",
         "sample": f"{len(idx)} of {batch.n_instances} instances x {len(heuristics)} heuristics "
                   f"({items} item placements), {dt:.2f} s wall on {cores} threads",
-    }, per_item
+    }, per_item, scored
 
 
 def best_of_orderings(V, torch, batch, crit, k, lb):
@@ -240,14 +272,19 @@ def main():
 
     per_kernel = {}
     for h in heuristics:
-        ops = OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[h] * items
+        ops = ops_per_item(h) * items
         achieved = ops / (kern_ms[h] / 1e3)
         per_kernel[h] = {"ms": round(kern_ms[h], 4),
                          "items_per_s": items / (kern_ms[h] / 1e3),
                          "alu_frac": achieved / ALU_PEAK}
     dom = max(heuristics, key=lambda h: kern_ms[h])
-    ops_dom = OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[dom] * items
+    ops_dom = ops_per_item(dom) * items
     achieved = ops_dom / (kern_ms[dom] / 1e3) / 1e12
+    work = f"({OPS_PER_BIN_TEST} ops x {BIN_TESTS_PER_ITEM[dom]} bin tests"
+    if dom in SCORED_DECISIONS_PER_ITEM:
+        work += (f" + {MLP_FMA_PER_DECISION} FMA x {SCORED_DECISIONS_PER_ITEM[dom]} scored "
+                 "decisions")
+    work += f") per item x {items} items"
     roofline = {
         "bound": "alu",
         "kernel": f"pack {dom}",
@@ -256,8 +293,7 @@ def main():
         "unit": "Tops/s",
         "frac": achieved / (ALU_PEAK / 1e12),
         "traffic": None,
-        "work_per_launch": f"{OPS_PER_BIN_TEST} ops x {BIN_TESTS_PER_ITEM[dom]} bin tests/item "
-                           f"x {items} items",
+        "work_per_launch": work,
     }
     out = {
         "metric": "items placed/sec, batched VSBPP heuristics; mean cost/LB, learned vs plain",
@@ -290,9 +326,10 @@ def main():
         "launch_shapes": {h: plans[h].launch() for h in heuristics},
     }
     if not args.no_cpu_baseline:
-        cb, per_item = cpu_baseline(batch, heuristics, args.cpu_sample)
+        cb, per_item, scored = cpu_baseline(batch, heuristics, args.cpu_sample)
         out["cpu_baseline"] = cb
         out["cpu_measured_bin_tests_per_item"] = per_item
+        out["cpu_measured_scored_decisions_per_item"] = scored
     print(json.dumps(out))
 
 
