@@ -130,10 +130,16 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
  *                            same offsets as the weights
  *   d_seeds[N] or NULL       per-instance generator keys (else opt->seed)
  * Bounds the caller guarantees (they size the launch):
- *   max_items     >= every m_i     (plain FF/BF/WF: the bins of one instance
- *                                   must fit in LDS, which limits max_items
- *                                   to about 26000, or 16000 when
- *                                   max_capacity > 32767)
+ *   max_items     >= every m_i     (plain FF/BF/WF: this call keeps the
+ *                                   bins of an instance in LDS, which limits
+ *                                   max_items to about 26000, or 13000 when
+ *                                   max_capacity > 32767 or max_items >
+ *                                   65535; beyond that it returns
+ *                                   VSBPP_E_SIZE, while plans and the
+ *                                   host-pointer calls keep the bins in a
+ *                                   device region they allocate instead.
+ *                                   The scorer and the decision hooks need
+ *                                   the bins in LDS.)
  *   max_types     >= every n_i, <= 16
  *   max_capacity  >= every B_1 of the batch
  * Outputs (device):
@@ -157,9 +163,11 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
 
 /* ------------------------------------------------------------------------ */
 /* Plans: a batch bound to its buffers, a heuristic and a launch shape, run   */
-/* any number of times.  A plan owns a small device workspace (a work        */
-/* counter and an instance schedule) allocated when it is created, so runs   */
-/* allocate nothing and may be captured into, or replayed from, a HIP graph. */
+/* any number of times.  A plan owns a device workspace (a work counter, an  */
+/* instance schedule and, for plain FF/BF/WF instances whose bins do not fit */
+/* LDS, max_items-sized arrays per instance) allocated when it is created,   */
+/* so runs allocate nothing and may be captured into, or replayed from, a    */
+/* HIP graph.                                                                */
 /* ------------------------------------------------------------------------ */
 
 /* A device-resident batch: the same CSR layout, bounds and outputs as the

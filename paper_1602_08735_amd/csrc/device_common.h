@@ -101,8 +101,10 @@ __device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
 // whose state starts at `seed`: the state seed + (k+1)*gamma through the
 // published 64-bit finaliser.
 // ---------------------------------------------------------------------------
+constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ull;
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-  uint64_t s = seed + (k + 1ull) * 0x9e3779b97f4a7c15ull;
+  uint64_t s = seed + (k + 1ull) * kGolden;
   s ^= s >> 30;
   s *= 0xbf58476d1ce4e5b9ull;
   s ^= s >> 27;
@@ -121,6 +123,20 @@ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t stream) {
 __device__ __forceinline__ int draw_criterion(uint64_t key, uint64_t counter) {
   uint64_t hi = splitmix64(key, counter) >> 32;
   return (int)((hi * 3ull) >> 32);
+}
+
+// The same draw from the generator's state s = key + (counter+1)*gamma, so a
+// run of consecutive counters advances s by gamma.  Only the high word of the
+// output is needed: hi32(x ^ (x >> 31)) = hi32(x) ^ (hi32(x) >> 31), and
+// floor(3h / 2^32) = [h >= ceil(2^32/3)] + [h >= ceil(2^33/3)].
+__device__ __forceinline__ int criterion_at_state(uint64_t s) {
+  s ^= s >> 30;
+  s *= 0xbf58476d1ce4e5b9ull;
+  s ^= s >> 27;
+  s *= 0x94d049bb133111ebull;
+  uint32_t hi = (uint32_t)(s >> 32);
+  hi ^= hi >> 31;
+  return (hi >= 0x55555556u ? 1 : 0) + (hi >= 0xAAAAAAABu ? 1 : 0);
 }
 
 // Rule 1 distribution: keyed permutation of [0,m) from a 4-round balanced

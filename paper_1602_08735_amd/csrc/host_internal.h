@@ -32,6 +32,12 @@ int32_t check_cfg(const LaunchCfg& c, int heuristic, const BatchArgs& a);
 LaunchCfg default_cfg(int heuristic, const BatchArgs& a);
 std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a);
 
+// Bytes of the device region a plain FF/BF/WF run needs when an instance's
+// bins do not fit a workgroup's LDS (num instances x the per-wavefront
+// arrays), 0 when they fit; -1 when they fit neither (decision hooks and the
+// scorer run from LDS only).  The region goes in BatchArgs::spill.
+int64_t plain_spill_bytes(const BatchArgs& a, int heuristic);
+
 // Enqueues one run: [queue reset] [LPT schedule] pack kernel.  `queue` and
 // `sched` are device workspace (may be null when the configuration needs
 // neither).  Returns a VSBPP_* code.

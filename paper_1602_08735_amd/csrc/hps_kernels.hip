@@ -524,6 +524,250 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
   }
 }
 
+// ---------------------------------------------------------------------------
+// Second heuristic with 32-bit bin words (B_1 <= 32767), the common case.
+//
+// Bin b of thread t is two words, in arrays A and W of the workgroup's LDS at
+// (b >> 2) * 4*blockDim + 4*t + (b & 3):
+//   A = room << 5 | b,   W = (R - room) << 5 | b,   R = 32767.
+// The candidate key of weight w in bin b (W5 = w << 5):
+//   BF: A - W5               least room after, then lowest b; a bin the item
+//                            does not fit wraps to >= 2^31
+//   WF: W + W5               most room after, then lowest b; no fit >= 2^20
+//   FF: (A - W5) & (2^31|31) the slot index b, or >= 2^31
+// Every fitting key is below 2^20 and every other one is not, so a placement
+// is one add, one mask and a minimum per bin, over the array its criterion
+// reads.  Slots without a bin hold room 0 (A = b, W = R << 5 | b): nothing
+// fits them.  The types of the bins opened after the n Rule-2 bins are 4-bit
+// fields of a register; the used-bin mask and the cost are kept as the items
+// go, so a packer needs no final pass over its bins.
+//
+// Rule-1 positions are resolved a chunk of rounds at a time by the whole
+// workgroup, and every packer starts from a per-instance template of its
+// Rule-2 bins.  A round (spr subsets) needs two barriers: one for the group
+// minimum, one before the winners' results are read.
+// ---------------------------------------------------------------------------
+constexpr int32_t kR5 = 32767;
+
+__device__ __forceinline__ int slot_word(int b, int stride) { return (b >> 2) * stride + (b & 3); }
+
+__global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int group) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ __align__(16) int32_t s_caps[kMaxTypes];
+  __shared__ uint32_t s_wmin[16];
+  __shared__ int s_flag;
+  __shared__ int s_slot;
+  const int tid = threadIdx.x, B = blockDim.x;
+  const int spr = B / group;  // subsets per round
+  const int stride = 4 * B;
+  int32_t* arrA = reinterpret_cast<int32_t*>(smem);
+  int32_t* arrW = arrA + (size_t)nbslots * B;
+  int32_t* tmplA = arrW + (size_t)nbslots * B;  // [nbslots]
+  int32_t* tmplW = tmplA + nbslots;             // [nbslots]
+  int32_t* s_ci = tmplW + nbslots;              // [B] chunk items
+  int32_t* s_cw = s_ci + B;                     // [B] chunk weights
+  int32_t* s_loc = s_cw + B;                    // [spr][6] canonical local ids
+  int32_t* s_typ = s_loc + spr * kMaxSubset;    // [spr][6] types of used bins
+  int32_t* s_u = s_typ + spr * kMaxSubset;      // [spr] used bins
+  int32_t* s_cst = s_u + spr;                   // [spr] subset cost
+  int32_t* myA = arrA + 4 * tid;
+  int32_t* myW = arrW + 4 * tid;
+  const int g = tid / group, r = tid - g * group;
+  const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
+
+  int cursor = blockIdx.x;
+  for (;;) {
+    const int slot = next_slot(a, &cursor, &s_slot);
+    if (slot >= a.num) break;
+    const int inst = a.sched ? a.sched[slot] : slot;
+    const int64_t off = a.item_off[inst];
+    const int64_t m64 = a.item_off[inst + 1] - off;
+    const int c0 = a.cap_off[inst];
+    const int n = a.cap_off[inst + 1] - c0;
+    const int m = m64 > 0x7FFFFFFF ? 0x7FFFFFFF : (int)m64;
+    const int err = m64 > a.max_items ? kErrSize
+                                       : validate_block(a, inst, off, m, c0, n, s_caps, &s_flag);
+    if (err) {
+      if (tid == 0) {
+        a.nbins[inst] = err;
+        a.cost[inst] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    // Rule 2 template: bins 0..n-1 empty with their capacity as room
+    if (tid < nbslots) {
+      const int32_t room = tid < n ? s_caps[tid] : 0;
+      tmplA[tid] = (room << 5) | tid;
+      tmplW[tid] = ((kR5 - room) << 5) | tid;
+    }
+    const uint64_t seed = inst_seed(a, inst);
+    Rule1Perm perm;
+    perm.init(seed, (uint32_t)m);
+    const uint64_t ck = stream_key(seed, kStreamH2);
+    const int S = min(a.s2, m);
+    const int P = factorial_small(S);
+    const int l = (m + S - 1) / S;
+    const int per_round = spr * S;
+    const int chunk_rounds = B / per_round;  // >= 1: group >= 64 >= S
+    const uint32_t pm_full = r < P ? nth_perm(r, S) : 0u;
+    int32_t carry = 0;
+    int64_t cost_acc = 0;
+    int cq = 0;  // first position of the current chunk
+    for (int base_I = 0, rnd = 0; base_I < l; base_I += spr, ++rnd) {
+      if (rnd % chunk_rounds == 0) {
+        // resolve the chunk's positions: item ids and weights
+        __syncthreads();
+        cq = base_I * S;
+        const int q = cq + tid;
+        if (tid < chunk_rounds * per_round && q < m) {
+          const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
+          s_ci[tid] = item;
+          s_cw[tid] = a.w[off + item];
+        }
+        __syncthreads();
+      }
+      const int I = base_I + g;
+      const int q0 = I * S;
+      const int k = I < l ? min(S, m - q0) : 0;
+      const int kf = factorial_small(k);
+      const bool active = k > 0 && r < kf;
+      const int lq = q0 - cq;  // the subset's first position in the chunk
+      uint32_t key = 0xFFFFFFFFu;
+      uint32_t used = 0, locs = 0;
+      uint64_t tl = 0;  // 4-bit types of bins n, n+1, ...
+      int32_t cost = 0;
+      if (active) {
+        for (int gi = 0; gi < (nbslots >> 2); ++gi) {
+          *reinterpret_cast<int4*>(myA + gi * stride) = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
+          *reinterpret_cast<int4*>(myW + gi * stride) = *reinterpret_cast<const int4*>(tmplW + 4 * gi);
+        }
+        const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
+        uint64_t st = ck + ((((uint64_t)I * (uint64_t)P + (uint64_t)r) * (uint64_t)S) + 1ull) * kGolden;
+        uint32_t div = 0;
+        int nb = n;
+        for (int t = 0; t < k; ++t) {
+          const int d = (pm >> (4 * t)) & 0xF;
+          const int32_t w = s_cw[lq + d];
+          const int crit = a.force_crit >= 0 ? a.force_crit : criterion_at_state(st);
+          st += kGolden;
+          const int32_t w5 = w << 5;
+          const int32_t* base = crit == WF ? myW : myA;
+          const int32_t x = crit == WF ? w5 : -w5;
+          const uint32_t msk = crit == FF ? 0x8000001Fu : 0xFFFFFFFFu;
+          // groups that can hold bins after t placements (each adds <= 2)
+          const int ng = (min(nbslots, n + 2 * t) + 3) >> 2;
+          // two groups per LDS round trip (an odd last group is read twice)
+          uint32_t best = 0xFFFFFFFFu;
+          for (int gi = 0; gi < ng; gi += 2) {
+            const int gj = gi + 1 < ng ? gi + 1 : gi;
+            const int4 v = *reinterpret_cast<const int4*>(base + gi * stride);
+            const int4 u = *reinterpret_cast<const int4*>(base + gj * stride);
+            const uint32_t k0 = (uint32_t)(v.x + x) & msk, k1 = (uint32_t)(v.y + x) & msk;
+            const uint32_t k2 = (uint32_t)(v.z + x) & msk, k3 = (uint32_t)(v.w + x) & msk;
+            const uint32_t k4 = (uint32_t)(u.x + x) & msk, k5 = (uint32_t)(u.y + x) & msk;
+            const uint32_t k6 = (uint32_t)(u.z + x) & msk, k7 = (uint32_t)(u.w + x) & msk;
+            best = min(best, min(k0, k1));
+            best = min(best, min(k2, k3));
+            best = min(best, min(k4, k5));
+            best = min(best, min(k6, k7));
+          }
+          int b, type;
+          int32_t room, cap;
+          if (best < (1u << 20)) {
+            b = (int)(best & 31u);
+            type = b < n ? b : (int)((tl >> (4 * (b - n))) & 0xFull);
+            const int32_t word = myA[slot_word(b, stride)];
+            cap = s_caps[type];
+            room = (word >> 5) - w;
+          } else {
+            // nothing fits: open a bin of the smallest capacity >= w (the
+            // capacities decrease, so it is the last of those >= w), or B_1
+            int cnt = 0;
+            int32_t cmin = 0x7FFFFFFF;
+            for (int kg = 0; kg < n; kg += 4) {
+              const int4 c4 = *reinterpret_cast<const int4*>(s_caps + kg);
+              const int32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const bool ge = kg + j < n && cv[j] >= w;
+                cnt += ge ? 1 : 0;
+                cmin = ge ? min(cmin, cv[j]) : cmin;
+              }
+            }
+            type = a.type_rule == 1 ? 0 : cnt - 1;
+            cap = a.type_rule == 1 ? s_caps[0] : cmin;
+            b = nb++;
+            tl |= (uint64_t)type << (4 * (b - n));
+            room = cap - w;
+          }
+          myA[slot_word(b, stride)] = (room << 5) | b;
+          myW[slot_word(b, stride)] = ((kR5 - room) << 5) | b;
+          if (!((used >> b) & 1u)) {
+            used |= 1u << b;
+            cost += cap;
+          }
+          // Rule 5: a bin at least half full divides once
+          if (!((div >> b) & 1u) && 2 * (cap - room) >= cap) {
+            div |= 1u << b;
+            const int nbn = nb++;
+            myA[slot_word(nbn, stride)] = (cap << 5) | nbn;
+            myW[slot_word(nbn, stride)] = ((kR5 - cap) << 5) | nbn;
+            tl |= (uint64_t)type << (4 * (nbn - n));
+          }
+          locs |= (uint32_t)b << (5 * d);
+        }
+        key = ((uint32_t)cost << 10) | (uint32_t)r;
+      }
+      // group minimum of (cost, rank): lowest rank on ties
+      uint32_t gm = wave_min(key);
+      if (lane == 0) s_wmin[wave] = gm;
+      __syncthreads();
+      gm = 0xFFFFFFFFu;
+      for (int i = 0; i < wpg; ++i) gm = min(gm, s_wmin[g * wpg + i]);
+      if (active && key == gm) {
+        for (int d = 0; d < k; ++d) {
+          const int b = (int)((locs >> (5 * d)) & 31u);
+          s_loc[g * kMaxSubset + d] = (int)__popc(used & ((1u << b) - 1u));
+        }
+        uint32_t uu = used;
+        int rr = 0;
+        while (uu) {
+          const int b = __builtin_ctz(uu);
+          uu &= uu - 1;
+          s_typ[g * kMaxSubset + rr] = b < n ? b : (int)((tl >> (4 * (b - n))) & 0xFull);
+          ++rr;
+        }
+        s_u[g] = rr;
+        s_cst[g] = cost;
+      }
+      if (r == 0 && k == 0) {
+        s_u[g] = 0;
+        s_cst[g] = 0;
+      }
+      __syncthreads();
+      // canonical ids: this subset's bins follow those of earlier subsets
+      int32_t before = carry, total = 0;
+      int64_t round_cost = 0;
+      for (int i = 0; i < spr; ++i) {
+        const int32_t ui = s_u[i];
+        before += i < g ? ui : 0;
+        total += ui;
+        round_cost += s_cst[i];
+      }
+      carry += total;
+      cost_acc += round_cost;
+      if (r < k) a.assign[off + s_ci[lq + r]] = before + s_loc[g * kMaxSubset + r];
+      if (k > 0 && r < s_u[g]) a.types[off + before + r] = s_typ[g * kMaxSubset + r];
+    }
+    if (tid == 0) {
+      a.nbins[inst] = carry;
+      a.cost[inst] = cost_acc;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename Kern>
 hipError_t raise_lds(Kern kern, size_t lds, bool& done) {
   if (lds > 65536 && !done) {
@@ -578,9 +822,12 @@ int h2_group(int s2) {
   return ((fact + 63) / 64) * 64;
 }
 
-size_t h2_lds_bytes(int nbslots, int block, int group, bool wide) {
+size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k) {
   const int spr = block / group;
-  return (size_t)block * (wide ? 2 : 1) * 4 * (size_t)nbslots +
+  if (k == H2Kernel::kSlim)  // bin arrays A and W, templates, chunk, per-subset results
+    return 4 * (2 * (size_t)nbslots * block + 2 * (size_t)nbslots + 2 * (size_t)block +
+                (size_t)spr * (2 * kMaxSubset + 2));
+  return (size_t)block * (k == H2Kernel::kWide ? 2 : 1) * 4 * (size_t)nbslots +
          (size_t)spr * (4 * kMaxSubset * 4 + 2 * 4) + (size_t)spr * 8;
 }
 
@@ -603,33 +850,30 @@ hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nbslots, int block,
   return hipGetLastError();
 }
 
-hipError_t launch_h1(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
-  return launch_h1_grid(a, wide, nbslots, block, 0, s);
-}
 
-hipError_t launch_h2_grid(const BatchArgs& a, bool wide, int nbslots, int block, int grid,
+hipError_t launch_h2_grid(const BatchArgs& a, H2Kernel k, int nbslots, int block, int grid,
                           hipStream_t s) {
   if (a.num <= 0) return hipSuccess;
   const int group = h2_group(a.s2);
   if (block < group) block = group;
   block = (block / group) * group;
-  const size_t lds = h2_lds_bytes(nbslots, block, group, wide);
+  const size_t lds = h2_lds_bytes(nbslots, block, group, k);
   const int blocks = grid > 0 ? grid : a.num;
   hipError_t e;
-  if (!wide) {
-    { static bool done3 = false; e = raise_lds(k_h2<uint32_t>, lds, done3); }
+  if (k == H2Kernel::kSlim) {
+    { static bool done3 = false; e = raise_lds(k_h2s, lds, done3); }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_h2s, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
+  } else if (k == H2Kernel::kPacked) {
+    { static bool done4 = false; e = raise_lds(k_h2<uint32_t>, lds, done4); }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_h2<uint32_t>, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
   } else {
-    { static bool done4 = false; e = raise_lds(k_h2<uint64_t>, lds, done4); }
+    { static bool done5 = false; e = raise_lds(k_h2<uint64_t>, lds, done5); }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_h2<uint64_t>, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
   }
   return hipGetLastError();
-}
-
-hipError_t launch_h2(const BatchArgs& a, bool wide, int nbslots, int block, hipStream_t s) {
-  return launch_h2_grid(a, wide, nbslots, block, 0, s);
 }
 
 namespace {
@@ -645,8 +889,10 @@ int h1_blocks_per_cu(bool wide, int block, size_t lds) {
   return wide ? occ(k_h1<uint64_t>, block, lds) : occ(k_h1<uint32_t>, block, lds);
 }
 
-int h2_blocks_per_cu(bool wide, int block, size_t lds) {
-  return wide ? occ(k_h2<uint64_t>, block, lds) : occ(k_h2<uint32_t>, block, lds);
+int h2_blocks_per_cu(H2Kernel k, int block, size_t lds) {
+  return k == H2Kernel::kSlim     ? occ(k_h2s, block, lds)
+         : k == H2Kernel::kPacked ? occ(k_h2<uint32_t>, block, lds)
+                                  : occ(k_h2<uint64_t>, block, lds);
 }
 
 namespace {

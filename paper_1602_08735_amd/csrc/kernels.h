@@ -43,6 +43,9 @@ struct BatchArgs {
   float* feat_out;          // [16*num], or null
   int32_t* info_out;        // [2*num], or null
   const vsbpp_model* model; // type_rule 2
+  // plain kernel: a device region of per-wave bytes per instance that holds
+  // the wavefront's arrays when they do not fit LDS, or null
+  unsigned char* spill;
 };
 
 // Next instance for a wavefront (plain kernel) or a workgroup (H1/H2): a
@@ -70,8 +73,6 @@ hipError_t allow_max_dynamic_lds(Kern kern) {
 constexpr int kStaticLdsReserve = 1024;
 
 // Launch helpers (defined next to their kernels).  They return a hipError_t.
-hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int waves_per_block,
-                        size_t lds_per_wave, hipStream_t s);
 // ext: decision hooks or the scorer in use
 size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext = false);
 size_t plain_lds_block_extra(bool learned);
@@ -79,12 +80,11 @@ inline bool plain_ext(const BatchArgs& a) {
   return a.src || a.force || a.feat_out || a.info_out || a.type_rule == 2;
 }
 size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide);
-size_t h2_lds_bytes(int nbslots, int block, int group, bool wide);
+// H2 kernels: two 32-bit words per bin (the fast form), one packed 32-bit
+// word per bin (when the fast form's LDS does not fit), 64-bit bins (wide)
+enum class H2Kernel { kSlim, kPacked, kWide };
+size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k);
 int h2_group(int s2);
-hipError_t launch_h1(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
-                     hipStream_t s);
-hipError_t launch_h2(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
-                     hipStream_t s);
 hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStream_t s);
 
 // per-instance (sum of weights, LB_cap, LB_big); LB_cap is exact when the
@@ -104,12 +104,12 @@ hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int waves_
                              size_t lds_per_wave, int grid, hipStream_t s);
 hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
                           int grid, hipStream_t s);
-hipError_t launch_h2_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
+hipError_t launch_h2_grid(const BatchArgs& a, H2Kernel k, int nb_regs, int block_threads,
                           int grid, hipStream_t s);
 // resident workgroups per CU for a launch shape (for persistent grids)
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int waves_per_block,
                         size_t lds_per_wave);
 int h1_blocks_per_cu(bool wide, int block_threads, size_t lds);
-int h2_blocks_per_cu(bool wide, int block_threads, size_t lds);
+int h2_blocks_per_cu(H2Kernel k, int block_threads, size_t lds);
 
 }  // namespace vsbpp

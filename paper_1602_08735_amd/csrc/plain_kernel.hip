@@ -274,8 +274,12 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   return v;
 }
 
-template <int CRIT, typename K, bool EXT>
-__global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per_wave) {
+// SPILL: the wavefront's arrays (keys, position->id map, suffix minima) sit
+// in a device region of per_wave bytes per instance instead of LDS, for
+// instances whose bins do not fit a workgroup's LDS (plain runs only).
+template <int CRIT, typename K, bool EXT, bool SPILL>
+__global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int64_t per_wave) {
+  static_assert(!(EXT && SPILL), "decision hooks and the scorer run from LDS");
   using KT = KeyT<K>;
   using Pid = typename KT::Pid;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -285,14 +289,21 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   // one aligned 16-byte word at an immediate offset from the lane's base
   ModelLds* md = reinterpret_cast<ModelLds*>(smem);
   const size_t model_bytes = (EXT && a.type_rule == 2) ? kModelLdsBytes : 0;
-  unsigned char* base = smem + model_bytes + (size_t)wave * lds_per_wave;
-  K* keys = reinterpret_cast<K*>(base);
   const size_t pid_bytes = ((size_t)a.slots * sizeof(Pid) + 15) & ~(size_t)15;
-  Pid* pid = reinterpret_cast<Pid*>(base + (size_t)a.slots * sizeof(K));
-  int32_t* smin = reinterpret_cast<int32_t*>(base + (size_t)a.slots * sizeof(K) + pid_bytes);
   const size_t smin_bytes = (((size_t)a.max_items + 63) / 64 * 4 + 15) & ~(size_t)15;
-  int32_t* hist = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(smin) + smin_bytes);
-  float* hbuf = reinterpret_cast<float*>(hist + 16);
+  K* keys;
+  Pid* pid;
+  int32_t* smin;
+  int32_t* hist;
+  float* hbuf;
+  auto carve = [&](unsigned char* base) {
+    keys = reinterpret_cast<K*>(base);
+    pid = reinterpret_cast<Pid*>(base + (size_t)a.slots * sizeof(K));
+    smin = reinterpret_cast<int32_t*>(base + (size_t)a.slots * sizeof(K) + pid_bytes);
+    hist = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(smin) + smin_bytes);
+    hbuf = reinterpret_cast<float*>(hist + 16);
+  };
+  if constexpr (!SPILL) carve(smem + model_bytes + (size_t)wave * (size_t)per_wave);
   ScorerRegs sr{};
   if constexpr (EXT) {
     if (a.type_rule == 2) {
@@ -315,6 +326,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
     }
     if (slot >= a.num) break;
     const int inst = a.sched ? uniform(a.sched[slot]) : slot;
+    if constexpr (SPILL) carve(a.spill + (size_t)inst * (size_t)per_wave);
     // inputs come from instance `src_i` (entries may share an instance)
     const int src_i = (EXT && a.src) ? uniform(a.src[inst]) : inst;
     const int64_t off = a.item_off[src_i];
@@ -375,6 +387,8 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
     int fd = -1, ft1 = -1, ft2 = -1, nev = 0;
     int64_t placed = 0;
     int32_t thr[5] = {0, 0, 0, 0, 0};
+    float xcap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float inv_cap_lane = 0.0f;
     if constexpr (EXT) {
       if (a.force) {
         fd = uniform(a.force[3 * (int64_t)inst]);
@@ -386,8 +400,16 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
 #pragma unroll
       for (int k = 1; k <= 5; ++k) thr[k - 1] = (int32_t)(((int64_t)k * (B1 + 1) + 5) / 6);
       if (lane < 8) hist[lane] = 0;
+      // features that are constants of the instance: B_2..B_5 over B_1, and
+      // lane k's 1/B_k for the fill of the smallest fitting type
+      const float inv_b1 = 1.0f / (float)B1;
+#pragma unroll
+      for (int k = 1; k <= 4; ++k)
+        xcap[k - 1] = k < n ? (float)readlane(cap_lane, k) * inv_b1 : 0.0f;
+      inv_cap_lane = lane < n ? 1.0f / (float)cap_lane : 0.0f;
     }
-    auto bucket = [&](int64_t r) -> int {
+    // rooms and capacities are int32
+    auto bucket = [&](int32_t r) -> int {
       int b = 0;
 #pragma unroll
       for (int k = 0; k < 5; ++k) b += r >= thr[k] ? 1 : 0;
@@ -487,7 +509,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
           const K rnew = room_of<CRIT>(nk);
           if (rnew < (K)T) ++dead;
           if constexpr (EXT) {
-            const int b0 = bucket((int64_t)rnew + w), b1 = bucket((int64_t)rnew);
+            const int b0 = bucket((int32_t)rnew + w), b1 = bucket((int32_t)rnew);
             if (b0 != b1 && lane == 0) {
               atomicAdd(&hist[b0], -1);
               atomicAdd(&hist[b1], 1);
@@ -527,9 +549,8 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
               x[9] = (float)h47.x * inv_den;
               x[10] = (float)h47.y * inv_den;
 #pragma unroll
-              for (int k = 1; k <= 4; ++k)
-                x[10 + k] = k < n ? (float)readlane(cap_lane, k) * inv_b1 : 0.0f;
-              x[15] = (float)w * (1.0f / (float)readlane(cap_lane, smallest));
+              for (int k = 0; k < 4; ++k) x[11 + k] = xcap[k];
+              x[15] = (float)w * __uint_as_float(readlane(__float_as_uint(inv_cap_lane), smallest));
               // with one type holding the item the scorer has nothing to choose
               if (a.type_rule == 2 && smallest > 0) {
                 const float z = mlp_forward_wave(md, sr, x, hbuf, lane);
@@ -576,7 +597,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
           cost += Bt;
           if (room < (K)T) ++dead;
           if constexpr (EXT) {
-            if (lane == 0) atomicAdd(&hist[bucket((int64_t)room)], 1);
+            if (lane == 0) atomicAdd(&hist[bucket((int32_t)room)], 1);
           }
         }
         if constexpr (EXT) placed += w;
@@ -593,10 +614,12 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int lds_per
   }
 }
 
-template <int CRIT, typename K, bool EXT>
-hipError_t launch_one(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid, hipStream_t s) {
-  const size_t lds = lds_per_wave * (size_t)wpb + (EXT ? plain_lds_block_extra(a.type_rule == 2) : 0);
-  auto kern = k_plain<CRIT, K, EXT>;
+template <int CRIT, typename K, bool EXT, bool SPILL>
+hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
+  const size_t lds = SPILL ? 0
+                           : per_wave * (size_t)wpb +
+                                 (EXT ? plain_lds_block_extra(a.type_rule == 2) : 0);
+  auto kern = k_plain<CRIT, K, EXT, SPILL>;
   static bool raised = false;
   if (lds > 65536 && !raised) {
     hipError_t e = allow_max_dynamic_lds(kern);
@@ -604,23 +627,31 @@ hipError_t launch_one(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid
     raised = true;
   }
   const int blocks = grid > 0 ? grid : (a.num + wpb - 1) / wpb;
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, a, wpb, (int)lds_per_wave);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, a, wpb, (int64_t)per_wave);
   return hipGetLastError();
 }
 
 template <int CRIT, typename K>
-hipError_t launch_sel(const BatchArgs& a, int wpb, size_t lds_per_wave, int grid, hipStream_t s) {
-  return plain_ext(a) ? launch_one<CRIT, K, true>(a, wpb, lds_per_wave, grid, s)
-                      : launch_one<CRIT, K, false>(a, wpb, lds_per_wave, grid, s);
+hipError_t launch_sel(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
+  if (a.spill) return launch_one<CRIT, K, false, true>(a, wpb, per_wave, grid, s);
+  return plain_ext(a) ? launch_one<CRIT, K, true, false>(a, wpb, per_wave, grid, s)
+                      : launch_one<CRIT, K, false, false>(a, wpb, per_wave, grid, s);
 }
 
 template <int CRIT, typename K>
-int occupancy(int wpb, size_t lds_per_wave, bool ext, bool learned) {
+int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill) {
   int n = 0;
-  const size_t lds = lds_per_wave * (size_t)wpb + (ext ? plain_lds_block_extra(learned) : 0);
-  const hipError_t e =
-      ext ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true>, 64 * wpb, lds)
-          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false>, 64 * wpb, lds);
+  hipError_t e;
+  if (spill) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, true>, 64 * wpb,
+                                                     0);
+  } else {
+    const size_t lds = per_wave * (size_t)wpb + (ext ? plain_lds_block_extra(learned) : 0);
+    e = ext ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false>,
+                                                           64 * wpb, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false>,
+                                                           64 * wpb, lds);
+  }
   if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
@@ -652,21 +683,17 @@ hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
   return launch_sel<WF, uint64_t>(a, wpb, lds_per_wave, grid, s);
 }
 
-hipError_t launch_plain(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave,
-                        hipStream_t s) {
-  return launch_plain_grid(a, crit, wide, wpb, lds_per_wave, 0, s);
-}
 
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave) {
-  const bool ext = plain_ext(a), learned = a.type_rule == 2;
+  const bool ext = plain_ext(a), learned = a.type_rule == 2, spill = a.spill != nullptr;
   if (!wide) {
-    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lds_per_wave, ext, learned);
-    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lds_per_wave, ext, learned);
-    return occupancy<WF, uint32_t>(wpb, lds_per_wave, ext, learned);
+    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lds_per_wave, ext, learned, spill);
+    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lds_per_wave, ext, learned, spill);
+    return occupancy<WF, uint32_t>(wpb, lds_per_wave, ext, learned, spill);
   }
-  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lds_per_wave, ext, learned);
-  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lds_per_wave, ext, learned);
-  return occupancy<WF, uint64_t>(wpb, lds_per_wave, ext, learned);
+  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lds_per_wave, ext, learned, spill);
+  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lds_per_wave, ext, learned, spill);
+  return occupancy<WF, uint64_t>(wpb, lds_per_wave, ext, learned, spill);
 }
 
 }  // namespace vsbpp

@@ -28,6 +28,7 @@ struct vsbpp_plan {
   int heuristic = 0;
   vsbpp::LaunchCfg cfg;
   int32_t* workspace = nullptr;  // [0] work counter, [1..num] schedule
+  unsigned char* spill = nullptr;  // plain runs whose bins do not fit LDS
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -217,6 +218,18 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
     delete p;
     return VSBPP_E_NOMEM;
   }
+  const int64_t spill = vsbpp::plain_spill_bytes(a, heuristic);
+  if (spill < 0) {
+    vsbpp_plan_destroy(p);
+    return VSBPP_E_SIZE;
+  }
+  if (spill > 0) {
+    if (hipMalloc(&p->spill, (size_t)spill) != hipSuccess) {
+      vsbpp_plan_destroy(p);
+      return VSBPP_E_NOMEM;
+    }
+    a.spill = p->spill;
+  }
   if (launch) {
     p->cfg.mode = launch->mode;
     p->cfg.lpt = launch->lpt;
@@ -285,6 +298,7 @@ void vsbpp_plan_destroy(vsbpp_plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->workspace) (void)hipFree(p->workspace);
+  if (p->spill) (void)hipFree(p->spill);
   delete p;
 }
 

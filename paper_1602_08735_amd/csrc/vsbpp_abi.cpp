@@ -114,6 +114,7 @@ struct PlainShape {
   int slots;
   size_t per_wave;
   int max_wpb;
+  bool spill;  // the per-wave arrays live in a device region, not LDS
 };
 
 int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
@@ -123,7 +124,12 @@ int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
   const bool ext = plain_ext(a);
   sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide, ext);
   const size_t extra = ext ? plain_lds_block_extra(a.type_rule == 2) : 0;
-  if ((size_t)device_info().max_lds_block < extra + sh->per_wave) return VSBPP_E_SIZE;
+  sh->spill = (size_t)device_info().max_lds_block < extra + sh->per_wave;
+  if (sh->spill) {
+    if (ext) return VSBPP_E_SIZE;
+    sh->max_wpb = 4;
+    return VSBPP_OK;
+  }
   sh->max_wpb = (int)(((size_t)device_info().max_lds_block - extra) / sh->per_wave);
   if (sh->max_wpb < 1) return VSBPP_E_SIZE;
   if (sh->max_wpb > 4) sh->max_wpb = 4;
@@ -134,11 +140,22 @@ int h_nbslots(int heuristic, const BatchArgs& a) {
   return round_up(a.max_types + 2 * (heuristic == VSBPP_H1 ? a.s1 : a.s2), 4);
 }
 
+// the H2 kernel for a workgroup size: two words per bin when they fit the
+// workgroup's LDS, else one packed word (64-bit bins for wide batches)
+H2Kernel h2_kernel(const BatchArgs& a, int block) {
+  if (is_wide(a)) return H2Kernel::kWide;
+  const size_t budget = (size_t)(device_info().max_lds_block - kStaticLdsReserve);
+  const int g = h2_group(a.s2);
+  const int b = block < g ? g : (block / g) * g;
+  return h2_lds_bytes(h_nbslots(VSBPP_H2, a), b, g, H2Kernel::kSlim) <= budget ? H2Kernel::kSlim
+                                                                                : H2Kernel::kPacked;
+}
+
 size_t h_lds(int heuristic, const BatchArgs& a, int block) {
   const bool wide = is_wide(a);
   const int nbs = h_nbslots(heuristic, a);
   return heuristic == VSBPP_H1 ? h1_lds_bytes(nbs, a.s1, block, wide)
-                               : h2_lds_bytes(nbs, block, h2_group(a.s2), wide);
+                               : h2_lds_bytes(nbs, block, h2_group(a.s2), h2_kernel(a, block));
 }
 
 // largest workgroup of the given granularity that fits the LDS budget
@@ -215,6 +232,13 @@ void set_last_error(const char* where, hipError_t e) {
                 (int)e);
 }
 
+int64_t plain_spill_bytes(const BatchArgs& a, int heuristic) {
+  if (heuristic > VSBPP_WF || a.num <= 0 || a.max_items < 1) return 0;
+  PlainShape sh;
+  if (plain_shape(a, &sh) != VSBPP_OK) return -1;
+  return sh.spill ? (int64_t)sh.per_wave * (int64_t)a.num : 0;
+}
+
 int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* queue,
                       int32_t* sched, hipStream_t s) {
   if (a.num <= 0) return VSBPP_OK;
@@ -238,6 +262,10 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     PlainShape sh;
     int32_t rc = plain_shape(a, &sh);
     if (rc != VSBPP_OK) return rc;
+    // arrays beyond LDS need the caller's device region (plans and the
+    // host-pointer calls provide one)
+    if (sh.spill && !a.spill) return VSBPP_E_SIZE;
+    if (!sh.spill) a.spill = nullptr;
     a.slots = sh.slots;
     const int wpb = c.wpb < sh.max_wpb ? c.wpb : sh.max_wpb;
     int grid = 0;
@@ -251,10 +279,10 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     if (c.mode == 1) {
       const size_t lds = h_lds(heuristic, a, block);
       grid = d.cus * (heuristic == VSBPP_H1 ? h1_blocks_per_cu(wide, block, lds)
-                                            : h2_blocks_per_cu(wide, block, lds));
+                                            : h2_blocks_per_cu(h2_kernel(a, block), block, lds));
     }
     e = heuristic == VSBPP_H1 ? launch_h1_grid(a, wide, nbs, block, grid, s)
-                              : launch_h2_grid(a, wide, nbs, block, grid, s);
+                              : launch_h2_grid(a, h2_kernel(a, block), nbs, block, grid, s);
   }
   if (e == hipSuccess) return VSBPP_OK;
 fail:
@@ -376,6 +404,13 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   a.force_crit = o.force_criterion;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
+  DevBuf<unsigned char> dspill;
+  const int64_t spill = plain_spill_bytes(a, heuristic);
+  if (spill < 0) return VSBPP_E_SIZE;
+  if (spill > 0) {
+    if (!dspill.alloc((size_t)spill)) return VSBPP_E_NOMEM;
+    a.spill = dspill.p;
+  }
   rc = launch_batch(a, heuristic, s);
   if (rc != VSBPP_OK) return rc;
   if (hipStreamSynchronize(s) != hipSuccess) return VSBPP_E_DEVICE;

@@ -127,3 +127,44 @@ def test_plan_rejects_bad_shapes(V):
         with pytest.raises(V.VsbppError) as e:
             V.Plan(db, h, launch=launch)
         assert e.value.code == -6
+
+
+def _big_batch(rng, sizes):
+    ws, cs = [], []
+    for m, b1 in sizes:
+        caps = np.concatenate([[b1], inputs._distinct_desc(rng, 1, b1 - 1, 3)]).astype(np.int32)
+        ws.append(rng.integers(1, b1 + 1, size=m).astype(np.int32))
+        cs.append(caps)
+    return inputs.make_batch(ws, cs, None, rng.integers(0, 2**63, size=len(sizes)).astype(np.uint64))
+
+
+@pytest.mark.parametrize("h", ("FF", "BF", "WF"))
+def test_bins_beyond_lds_use_a_device_region(V, orc, h):
+    """Instances whose bins do not fit a workgroup's LDS -- 30000 items with
+    32-bit keys, 20000 items with capacities above 32767 (64-bit keys) -- run
+    from a device region: through plans in every launch mode and through the
+    host-pointer call, bit for bit.  The allocation-free batch call declines
+    them with VSBPP_E_SIZE."""
+    import torch
+
+    rng = np.random.default_rng(950 + ("FF", "BF", "WF").index(h))
+    for sizes in (((30000, 1000), (26500, 300)), ((20000, 100000),)):
+        b = _big_batch(rng, sizes)
+        expected = oracle_batch(b, h)
+        db = V.DeviceBatch(b)
+        for launch in (dict(mode=0, waves_per_block=1), dict(mode=1, lpt=1, waves_per_block=4)):
+            db.assignment.fill_(-1)
+            db.nbins.fill_(0)
+            print("big", h, sizes, launch, flush=True)
+            p = V.Plan(db, h, launch=launch)
+            p.run()
+            torch.cuda.synchronize()
+            assert_batch_equal(b, db, expected)
+            p.close()
+        with pytest.raises(V.VsbppError) as e:
+            V.pack_batch(db, h)
+        assert e.value.code == -2
+        w, caps, _ = b.instance(0)
+        r = V.pack(w, caps, h)
+        o = orc.pack(w, caps, h)
+        assert r.cost == o.cost and np.array_equal(r.assignment, o.assignment)
