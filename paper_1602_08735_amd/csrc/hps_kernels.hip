@@ -542,14 +542,17 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 // fields of a register; the used-bin mask and the cost are kept as the items
 // go, so a packer needs no final pass over its bins.
 //
-// Rule-1 positions are resolved a chunk of rounds at a time by the whole
-// workgroup, and every packer starts from a per-instance template of its
-// Rule-2 bins.  A round (spr subsets) needs two barriers: one for the group
+// Rule-1 positions, their weights and the bin each item opens when nothing
+// fits are resolved a chunk of rounds at a time by the whole workgroup, and
+// every packer starts from a per-instance template of its Rule-2 bins.  A round (spr subsets) needs two barriers: one for the group
 // minimum, one before the winners' results are read.
 // ---------------------------------------------------------------------------
 constexpr int32_t kR5 = 32767;
 
-__device__ __forceinline__ int slot_word(int b, int stride) { return (b >> 2) * stride + (b & 3); }
+// word of slot b; (b >> 2) * stride < 2^24 and stride is a multiple of 4
+__device__ __forceinline__ int slot_word(int b, int stride) {
+  return (int)(__umul24((unsigned)(b >> 2), (unsigned)stride) | (unsigned)(b & 3));
+}
 
 __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int group) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -566,7 +569,8 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   int32_t* tmplW = tmplA + nbslots;             // [nbslots]
   int32_t* s_ci = tmplW + nbslots;              // [B] chunk items
   int32_t* s_cw = s_ci + B;                     // [B] chunk weights
-  int32_t* s_loc = s_cw + B;                    // [spr][6] canonical local ids
+  int32_t* s_ct = s_cw + B;                     // [B] type << 16 | capacity of a new bin
+  int32_t* s_loc = s_ct + B;                    // [spr][6] canonical local ids
   int32_t* s_typ = s_loc + spr * kMaxSubset;    // [spr][6] types of used bins
   int32_t* s_u = s_typ + spr * kMaxSubset;      // [spr] used bins
   int32_t* s_cst = s_u + spr;                   // [spr] subset cost
@@ -622,8 +626,15 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
         const int q = cq + tid;
         if (tid < chunk_rounds * per_round && q < m) {
           const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
+          const int32_t w = a.w[off + item];
           s_ci[tid] = item;
-          s_cw[tid] = a.w[off + item];
+          s_cw[tid] = w;
+          // the bin this item opens when nothing fits: the smallest capacity
+          // >= w (the capacities decrease, so the last of those), or B_1
+          int t = 0;
+          if (a.type_rule != 1)
+            for (int kk = 1; kk < n; ++kk) t += s_caps[kk] >= w ? 1 : 0;
+          s_ct[tid] = (t << 16) | s_caps[t];
         }
         __syncthreads();
       }
@@ -649,6 +660,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
           const int32_t w = s_cw[lq + d];
+          const int32_t tc = s_ct[lq + d];
           const int crit = a.force_crit >= 0 ? a.force_crit : criterion_at_state(st);
           st += kGolden;
           const int32_t w5 = w << 5;
@@ -681,22 +693,9 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
             cap = s_caps[type];
             room = (word >> 5) - w;
           } else {
-            // nothing fits: open a bin of the smallest capacity >= w (the
-            // capacities decrease, so it is the last of those >= w), or B_1
-            int cnt = 0;
-            int32_t cmin = 0x7FFFFFFF;
-            for (int kg = 0; kg < n; kg += 4) {
-              const int4 c4 = *reinterpret_cast<const int4*>(s_caps + kg);
-              const int32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const bool ge = kg + j < n && cv[j] >= w;
-                cnt += ge ? 1 : 0;
-                cmin = ge ? min(cmin, cv[j]) : cmin;
-              }
-            }
-            type = a.type_rule == 1 ? 0 : cnt - 1;
-            cap = a.type_rule == 1 ? s_caps[0] : cmin;
+            // nothing fits: open the item's bin type (resolved with its chunk)
+            type = tc >> 16;
+            cap = tc & 0xFFFF;
             b = nb++;
             tl |= (uint64_t)type << (4 * (b - n));
             room = cap - w;
@@ -825,7 +824,7 @@ int h2_group(int s2) {
 size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k) {
   const int spr = block / group;
   if (k == H2Kernel::kSlim)  // bin arrays A and W, templates, chunk, per-subset results
-    return 4 * (2 * (size_t)nbslots * block + 2 * (size_t)nbslots + 2 * (size_t)block +
+    return 4 * (2 * (size_t)nbslots * block + 2 * (size_t)nbslots + 3 * (size_t)block +
                 (size_t)spr * (2 * kMaxSubset + 2));
   return (size_t)block * (k == H2Kernel::kWide ? 2 : 1) * 4 * (size_t)nbslots +
          (size_t)spr * (4 * kMaxSubset * 4 + 2 * 4) + (size_t)spr * 8;
