@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--items", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--heuristics", default=",".join(HEURISTICS + LEARNED))
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")

@@ -192,7 +192,7 @@ typedef struct vsbpp_batch {
  * resident workgroups taking instances from a device work counter.  lpt = 1
  * processes instances by decreasing item count (largest first, for uneven
  * batches; batches up to 8192 instances).  waves_per_block: FF/BF/WF
- * wavefronts (one instance each) per workgroup, 1..4.  block_threads: H1/H2
+ * wavefronts (one instance each) per workgroup, 1..8.  block_threads: H1/H2
  * workgroup size (H2: a multiple of roundup(s2!, 64)). */
 typedef struct vsbpp_launch {
   int32_t mode;

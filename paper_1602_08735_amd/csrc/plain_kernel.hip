@@ -135,75 +135,77 @@ __device__ int compact(K* keys, typename KeyT<K>::Pid* pid, int nlive, int32_t T
 // inputs 8g..8g+7 of output k, and lane k adds its bias and the eight
 // partials in order g = 0..7.
 //
-// Row l of W1 and W2 (and b1[l], b2[l]) stays in lane l's registers for the
-// wavefront's lifetime, so a decision reads no hidden-layer weight from
-// memory; only the activations go through LDS (16-byte broadcasts).  The
-// output layer, which needs up to 16 outputs, is staged per workgroup in LDS.
+// The model is staged once per workgroup at the start of LDS as fp32, laid
+// out so that lane l reads its rows of W1 and W2 as unit-stride 16-byte words
+// at immediate offsets.  Keeping the weights out of registers holds a scorer
+// wavefront under 128 VGPRs, so four of them fit a SIMD and a batch of one
+// instance per wavefront runs in a single wave of residency.
 // ---------------------------------------------------------------------------
 struct ModelLds {
+  float w1[4 * 64 * 4];    // [i/4][l][4]
+  float w2[16 * 64 * 4];   // [j/4][l][4]
   float w3[16 * 8 * 8];    // [k][g][8]
-  float b3[16];
+  float b1[64], b2[64], b3[16];
   int32_t n_out;
 };
 
 constexpr size_t kModelLdsBytes = (sizeof(ModelLds) + 15) & ~(size_t)15;
 
-struct ScorerRegs {
-  float w1[16];
-  float w2[64];
-  float b1, b2;
-};
-
 __device__ __forceinline__ float bf16f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
 __device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
+  for (int e = threadIdx.x; e < 64 * 16; e += blockDim.x) {
+    const int l = e >> 4, i = e & 15;
+    s->w1[(((i >> 2) * 64) + l) * 4 + (i & 3)] = bf16f(m->w1[e]);
+  }
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    const int l = e >> 6, j = e & 63;
+    s->w2[(((j >> 2) * 64) + l) * 4 + (j & 3)] = bf16f(m->w2[e]);
+  }
   for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) s->w3[e] = bf16f(m->w3[e]);
-  for (int e = threadIdx.x; e < 16; e += blockDim.x) s->b3[e] = m->b3[e];
+  for (int e = threadIdx.x; e < 64; e += blockDim.x) {
+    s->b1[e] = m->b1[e];
+    s->b2[e] = m->b2[e];
+    if (e < 16) s->b3[e] = m->b3[e];
+  }
   if (threadIdx.x == 0) {
     const int n = m->n_out;
     s->n_out = n < 1 ? 1 : (n > 16 ? 16 : n);
   }
 }
 
-__device__ void load_scorer_regs(const vsbpp_model* m, int lane, ScorerRegs& r) {
-  // rows start 4-byte aligned: two bf16 weights per load
-  const uint32_t* r1 = reinterpret_cast<const uint32_t*>(&m->w1[lane * 16]);
-  const uint32_t* r2 = reinterpret_cast<const uint32_t*>(&m->w2[lane * 64]);
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint32_t v = r1[i];
-    r.w1[2 * i] = bf16f(v & 0xFFFFu);
-    r.w1[2 * i + 1] = __uint_as_float(v & 0xFFFF0000u);
-  }
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const uint32_t v = r2[j];
-    r.w2[2 * j] = bf16f(v & 0xFFFFu);
-    r.w2[2 * j + 1] = __uint_as_float(v & 0xFFFF0000u);
-  }
-  r.b1 = m->b1[lane];
-  r.b2 = m->b2[lane];
-}
-
 // Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
 // x: wave-uniform features; hbuf: 128 floats of LDS scratch of this wavefront.
-__device__ float mlp_forward_wave(const ModelLds* md, const ScorerRegs& r, const float (&x)[16],
-                                  float* hbuf, int lane) {
-  float acc = r.b1;
+__device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], float* hbuf,
+                                  int lane) {
+  float acc = md->b1[lane];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc = __builtin_fmaf(r.w1[i], x[i], acc);
+  for (int ib = 0; ib < 4; ++ib) {
+    const float4 wv = *reinterpret_cast<const float4*>(&md->w1[(ib * 64 + lane) * 4]);
+    acc = __builtin_fmaf(wv.x, x[ib * 4], acc);
+    acc = __builtin_fmaf(wv.y, x[ib * 4 + 1], acc);
+    acc = __builtin_fmaf(wv.z, x[ib * 4 + 2], acc);
+    acc = __builtin_fmaf(wv.w, x[ib * 4 + 3], acc);
+  }
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
-  acc = r.b2;
-  // all sixteen broadcasts are issued before the chain: one LDS round trip
-  float4 hv[16];
+  acc = md->b2[lane];
+  // weights (this lane's row) and activations (broadcasts), four 16-byte
+  // words of each per LDS round trip
 #pragma unroll
-  for (int jb = 0; jb < 16; ++jb) hv[jb] = *reinterpret_cast<const float4*>(&hbuf[jb * 4]);
+  for (int jo = 0; jo < 16; jo += 4) {
+    float4 wv[4], hv[4];
 #pragma unroll
-  for (int jb = 0; jb < 16; ++jb) {
-    acc = __builtin_fmaf(r.w2[jb * 4], hv[jb].x, acc);
-    acc = __builtin_fmaf(r.w2[jb * 4 + 1], hv[jb].y, acc);
-    acc = __builtin_fmaf(r.w2[jb * 4 + 2], hv[jb].z, acc);
-    acc = __builtin_fmaf(r.w2[jb * 4 + 3], hv[jb].w, acc);
+    for (int jb = 0; jb < 4; ++jb) {
+      wv[jb] = *reinterpret_cast<const float4*>(&md->w2[((jo + jb) * 64 + lane) * 4]);
+      hv[jb] = *reinterpret_cast<const float4*>(&hbuf[(jo + jb) * 4]);
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      acc = __builtin_fmaf(wv[jb].x, hv[jb].x, acc);
+      acc = __builtin_fmaf(wv[jb].y, hv[jb].y, acc);
+      acc = __builtin_fmaf(wv[jb].z, hv[jb].z, acc);
+      acc = __builtin_fmaf(wv[jb].w, hv[jb].w, acc);
+    }
   }
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
   float* part = hbuf + 64;
@@ -278,7 +280,7 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 // in a device region of per_wave bytes per instance instead of LDS, for
 // instances whose bins do not fit a workgroup's LDS (plain runs only).
 template <int CRIT, typename K, bool EXT, bool SPILL>
-__global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int64_t per_wave) {
+__global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per_wave) {
   static_assert(!(EXT && SPILL), "decision hooks and the scorer run from LDS");
   using KT = KeyT<K>;
   using Pid = typename KT::Pid;
@@ -304,11 +306,9 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int64_t per
     hbuf = reinterpret_cast<float*>(hist + 16);
   };
   if constexpr (!SPILL) carve(smem + model_bytes + (size_t)wave * (size_t)per_wave);
-  ScorerRegs sr{};
   if constexpr (EXT) {
     if (a.type_rule == 2) {
       stage_model(a.model, md);
-      load_scorer_regs(a.model, lane, sr);
       __syncthreads();
     }
   }
@@ -553,7 +553,7 @@ __global__ void __launch_bounds__(256) k_plain(BatchArgs a, int wpb, int64_t per
               x[15] = (float)w * __uint_as_float(readlane(__float_as_uint(inv_cap_lane), smallest));
               // with one type holding the item the scorer has nothing to choose
               if (a.type_rule == 2 && smallest > 0) {
-                const float z = mlp_forward_wave(md, sr, x, hbuf, lane);
+                const float z = mlp_forward_wave(md, x, hbuf, lane);
                 const int kmax = min(n, md->n_out);
                 // lanes 0..kmax-1 hold the scores; the choice is the lowest
                 // feasible type whose score equals the largest feasible score

@@ -127,12 +127,12 @@ int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
   sh->spill = (size_t)device_info().max_lds_block < extra + sh->per_wave;
   if (sh->spill) {
     if (ext) return VSBPP_E_SIZE;
-    sh->max_wpb = 4;
+    sh->max_wpb = 8;
     return VSBPP_OK;
   }
   sh->max_wpb = (int)(((size_t)device_info().max_lds_block - extra) / sh->per_wave);
   if (sh->max_wpb < 1) return VSBPP_E_SIZE;
-  if (sh->max_wpb > 4) sh->max_wpb = 4;
+  if (sh->max_wpb > 8) sh->max_wpb = 8;
   return VSBPP_OK;
 }
 
@@ -175,7 +175,7 @@ int32_t check_cfg(const LaunchCfg& c, int heuristic, const BatchArgs& a) {
   if (c.mode < 0 || c.mode > 1 || c.lpt < 0 || c.lpt > 1) return VSBPP_E_OPTION;
   if (c.lpt && a.num > kLptMax) return VSBPP_E_OPTION;
   if (heuristic <= VSBPP_WF) {
-    if (c.wpb < 1 || c.wpb > 4) return VSBPP_E_OPTION;
+    if (c.wpb < 1 || c.wpb > 8) return VSBPP_E_OPTION;
   } else {
     if (c.block < 64 || c.block > 1024 || (c.block & 63)) return VSBPP_E_OPTION;
     if (heuristic == VSBPP_H2 && (c.block % h2_group(a.s2))) return VSBPP_E_OPTION;
@@ -202,7 +202,7 @@ std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a) {
   for (int mode = 0; mode <= 1; ++mode) {
     for (int lpt = 0; lpt <= (lpt_ok ? 1 : 0); ++lpt) {
       if (heuristic <= VSBPP_WF) {
-        for (int wpb : {1, 2, 4}) {
+        for (int wpb : {1, 2, 4, 8}) {
           LaunchCfg c;
           c.mode = mode;
           c.lpt = lpt;

@@ -46,7 +46,7 @@ def _launches(h):
     for mode in (0, 1):
         for lpt in (0, 1):
             if h in ("FF", "BF", "WF"):
-                out += [dict(mode=mode, lpt=lpt, waves_per_block=w) for w in (1, 2, 4)]
+                out += [dict(mode=mode, lpt=lpt, waves_per_block=w) for w in (1, 2, 4, 8)]
             elif h == "H1":
                 out += [dict(mode=mode, lpt=lpt, block_threads=b) for b in (64, 256, 1024)]
             else:
@@ -122,7 +122,7 @@ def test_autotuned_plans(V, orc, tmp_path):
 def test_plan_rejects_bad_shapes(V):
     b = inputs.config2(n_instances=8, m=50)
     db = V.DeviceBatch(b)
-    for h, launch in (("FF", dict(waves_per_block=5)), ("H1", dict(block_threads=100)),
+    for h, launch in (("FF", dict(waves_per_block=9)), ("H1", dict(block_threads=100)),
                       ("H2", dict(block_threads=64)), ("BF", dict(mode=2))):
         with pytest.raises(V.VsbppError) as e:
             V.Plan(db, h, launch=launch)
