@@ -536,7 +536,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
               float x[16];
               x[0] = (float)w * inv_b1;
               x[1] = (float)rem * inv_m;
-              x[2] = rem > 0 ? ((float)rsum / (float)rem) * inv_b1 : 0.0f;
+              // with 32-bit keys m <= 65535 and B_1 <= 32767, so the remaining
+              // weight fits int32 (whose conversion rounds as int64's does)
+              const float frs = sizeof(K) == 4 ? (float)(int32_t)rsum : (float)rsum;
+              x[2] = rem > 0 ? (frs / (float)rem) * inv_b1 : 0.0f;
               x[3] = rem > 0 ? (float)after * inv_b1 : 1.0f;
               x[4] = (float)nb * inv_m;
               const float inv_den = 1.0f / (float)(nb > 0 ? nb : 1);
