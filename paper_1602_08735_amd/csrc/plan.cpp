@@ -83,7 +83,10 @@ int32_t run_eager(vsbpp_plan* p, hipStream_t s) {
   return vsbpp::enqueue_batch(p->args, p->heuristic, p->cfg, p->workspace, p->workspace + 1, s);
 }
 
-// Times every candidate shape on the batch itself and returns the fastest.
+// Times every candidate shape on the batch itself and returns the fastest:
+// the least of five timed runs after a warm-up run, then the three best
+// candidates timed again the same way (launch times of one shape vary by a
+// few percent from run to run, so a single pass can rank close shapes wrongly).
 int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
   hipStream_t s = nullptr;
   if (hipStreamCreate(&s) != hipSuccess) return VSBPP_E_DEVICE;
@@ -92,33 +95,56 @@ int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
     (void)hipStreamDestroy(s);
     return VSBPP_E_DEVICE;
   }
-  float best_ms = 1e30f;
   int32_t rc = VSBPP_OK;
-  bool found = false;
-  for (const vsbpp::LaunchCfg& c : vsbpp::candidate_cfgs(p->heuristic, p->args)) {
+  // least time of five runs of shape c, or a negative value when c does not
+  // apply to the batch
+  auto time_cfg = [&](const vsbpp::LaunchCfg& c, float* out) -> int32_t {
     p->cfg = c;
-    rc = run_eager(p, s);  // warm-up
-    if (rc == VSBPP_E_SIZE || rc == VSBPP_E_OPTION) continue;
-    if (rc != VSBPP_OK) break;
-    float t[3];
-    for (float& ti : t) {
-      (void)hipEventRecord(e0, s);
-      rc = run_eager(p, s);
-      (void)hipEventRecord(e1, s);
-      if (rc != VSBPP_OK || hipEventSynchronize(e1) != hipSuccess) {
-        rc = rc != VSBPP_OK ? rc : VSBPP_E_DEVICE;
-        break;
-      }
-      (void)hipEventElapsedTime(&ti, e0, e1);
+    int32_t r = run_eager(p, s);  // warm-up
+    if (r == VSBPP_E_SIZE || r == VSBPP_E_OPTION) {
+      *out = -1.0f;
+      return VSBPP_OK;
     }
+    if (r != VSBPP_OK) return r;
+    float tmin = 1e30f;
+    for (int i = 0; i < 5; ++i) {
+      (void)hipEventRecord(e0, s);
+      r = run_eager(p, s);
+      (void)hipEventRecord(e1, s);
+      if (r != VSBPP_OK) return r;
+      if (hipEventSynchronize(e1) != hipSuccess) return VSBPP_E_DEVICE;
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      tmin = std::min(tmin, t);
+    }
+    *out = tmin;
+    return VSBPP_OK;
+  };
+  std::vector<std::pair<float, vsbpp::LaunchCfg>> timed;
+  for (const vsbpp::LaunchCfg& c : vsbpp::candidate_cfgs(p->heuristic, p->args)) {
+    float t = 0.0f;
+    rc = time_cfg(c, &t);
     if (rc != VSBPP_OK) break;
-    std::sort(t, t + 3);
-    if (t[1] < best_ms) {
-      best_ms = t[1];
-      *best = c;
-      found = true;
+    if (t >= 0.0f) timed.emplace_back(t, c);
+  }
+  if (rc == VSBPP_OK && !timed.empty()) {
+    std::stable_sort(timed.begin(), timed.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    if (timed.size() > 3) timed.resize(3);
+    for (auto& tc : timed) {
+      float t = 0.0f;
+      rc = time_cfg(tc.second, &t);
+      if (rc != VSBPP_OK) break;
+      tc.first = std::min(tc.first, t);
+    }
+    if (rc == VSBPP_OK) {
+      const auto it = std::min_element(timed.begin(), timed.end(), [](const auto& x, const auto& y) {
+        return x.first < y.first;
+      });
+      *best = it->second;
     }
   }
+  const bool found = !timed.empty();
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
