@@ -528,19 +528,21 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 // Second heuristic with 32-bit bin words (B_1 <= 32767), the common case.
 //
 // Bin b of thread t is two words, in arrays A and W of the workgroup's LDS at
-// (b >> 2) * 4*blockDim + 4*t + (b & 3):
-//   A = room << 5 | b,   W = (R - room) << 5 | b,   R = 32767.
-// The candidate key of weight w in bin b (W5 = w << 5):
-//   BF: A - W5               least room after, then lowest b; a bin the item
-//                            does not fit wraps to >= 2^31
-//   WF: W + W5               most room after, then lowest b; no fit >= 2^20
-//   FF: (A - W5) & (2^31|31) the slot index b, or >= 2^31
-// Every fitting key is below 2^20 and every other one is not, so a placement
+// (b >> 2) * 4*blockDim + 4*t + (b & 3), with the bin's type k < 16:
+//   A = room << 10 | b << 5 | k,   W = (R - room) << 10 | b << 5 | k,
+//   R = 32767.
+// The candidate key of weight w in bin b (W10 = w << 10):
+//   BF: A - W10                  least room after, then lowest b; a bin the
+//                                item does not fit wraps to >= 2^31
+//   WF: W + W10                  most room after, then lowest b; no fit
+//                                >= 2^25
+//   FF: (A - W10) & (2^31|1023)  b << 5 | k, or >= 2^31
+// Every fitting key is below 2^25 and every other one is not, so a placement
 // is one add, one mask and a minimum per bin, over the array its criterion
-// reads.  Slots without a bin hold room 0 (A = b, W = R << 5 | b): nothing
-// fits them.  The types of the bins opened after the n Rule-2 bins are 4-bit
-// fields of a register; the used-bin mask and the cost are kept as the items
-// go, so a packer needs no final pass over its bins.
+// reads, and the least key also names the bin's type.  Slots without a bin
+// hold room 0 (A = b << 5, W = R << 10 | b << 5): nothing fits them.  The
+// used-bin mask and the cost are kept as the items go, so a packer needs no
+// final pass over its bins.
 //
 // Rule-1 positions, their weights and the bin each item opens when nothing
 // fits are resolved a chunk of rounds at a time by the whole workgroup, and
@@ -602,8 +604,9 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
     // Rule 2 template: bins 0..n-1 empty with their capacity as room
     if (tid < nbslots) {
       const int32_t room = tid < n ? s_caps[tid] : 0;
-      tmplA[tid] = (room << 5) | tid;
-      tmplW[tid] = ((kR5 - room) << 5) | tid;
+      const int32_t tag = (tid << 5) | (tid < n ? tid : 0);
+      tmplA[tid] = (room << 10) | tag;
+      tmplW[tid] = ((kR5 - room) << 10) | tag;
     }
     const uint64_t seed = inst_seed(a, inst);
     Rule1Perm perm;
@@ -646,7 +649,6 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       const int lq = q0 - cq;  // the subset's first position in the chunk
       uint32_t key = 0xFFFFFFFFu;
       uint32_t used = 0, locs = 0;
-      uint64_t tl = 0;  // 4-bit types of bins n, n+1, ...
       int32_t cost = 0;
       if (active) {
         for (int gi = 0; gi < (nbslots >> 2); ++gi) {
@@ -663,10 +665,10 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const int32_t tc = s_ct[lq + d];
           const int crit = a.force_crit >= 0 ? a.force_crit : criterion_at_state(st);
           st += kGolden;
-          const int32_t w5 = w << 5;
+          const int32_t w10 = w << 10;
           const int32_t* base = crit == WF ? myW : myA;
-          const int32_t x = crit == WF ? w5 : -w5;
-          const uint32_t msk = crit == FF ? 0x8000001Fu : 0xFFFFFFFFu;
+          const int32_t x = crit == WF ? w10 : -w10;
+          const uint32_t msk = crit == FF ? 0x800003FFu : 0xFFFFFFFFu;
           // groups that can hold bins after t placements (each adds <= 2)
           const int ng = (min(nbslots, n + 2 * t) + 3) >> 2;
           // two groups per LDS round trip (an odd last group is read twice)
@@ -686,22 +688,22 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           }
           int b, type;
           int32_t room, cap;
-          if (best < (1u << 20)) {
-            b = (int)(best & 31u);
-            type = b < n ? b : (int)((tl >> (4 * (b - n))) & 0xFull);
+          if (best < (1u << 25)) {
+            b = (int)((best >> 5) & 31u);
+            type = (int)(best & 31u);
             const int32_t word = myA[slot_word(b, stride)];
             cap = s_caps[type];
-            room = (word >> 5) - w;
+            room = (word >> 10) - w;
           } else {
             // nothing fits: open the item's bin type (resolved with its chunk)
             type = tc >> 16;
             cap = tc & 0xFFFF;
             b = nb++;
-            tl |= (uint64_t)type << (4 * (b - n));
             room = cap - w;
           }
-          myA[slot_word(b, stride)] = (room << 5) | b;
-          myW[slot_word(b, stride)] = ((kR5 - room) << 5) | b;
+          const int32_t tag = (b << 5) | type;
+          myA[slot_word(b, stride)] = (room << 10) | tag;
+          myW[slot_word(b, stride)] = ((kR5 - room) << 10) | tag;
           if (!((used >> b) & 1u)) {
             used |= 1u << b;
             cost += cap;
@@ -710,9 +712,9 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           if (!((div >> b) & 1u) && 2 * (cap - room) >= cap) {
             div |= 1u << b;
             const int nbn = nb++;
-            myA[slot_word(nbn, stride)] = (cap << 5) | nbn;
-            myW[slot_word(nbn, stride)] = ((kR5 - cap) << 5) | nbn;
-            tl |= (uint64_t)type << (4 * (nbn - n));
+            const int32_t tagn = (nbn << 5) | type;
+            myA[slot_word(nbn, stride)] = (cap << 10) | tagn;
+            myW[slot_word(nbn, stride)] = ((kR5 - cap) << 10) | tagn;
           }
           locs |= (uint32_t)b << (5 * d);
         }
@@ -734,7 +736,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
         while (uu) {
           const int b = __builtin_ctz(uu);
           uu &= uu - 1;
-          s_typ[g * kMaxSubset + rr] = b < n ? b : (int)((tl >> (4 * (b - n))) & 0xFull);
+          s_typ[g * kMaxSubset + rr] = myA[slot_word(b, stride)] & 31;
           ++rr;
         }
         s_u[g] = rr;
