@@ -580,8 +580,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
                 }
               }
             }
-            const int ft = d == fd ? ft1 : (fd >= 0 && d == fd + 1 ? ft2 : -1);
-            if (ft >= 0 && ft < n && ((fm >> ft) & 1ull)) t = ft;
+            if (fd >= 0) {  // forced decisions (rollouts) only
+              const int ft = d == fd ? ft1 : (d == fd + 1 ? ft2 : -1);
+              if (ft >= 0 && ft < n && ((fm >> ft) & 1ull)) t = ft;
+            }
           }
           const int32_t Bt = readlane(cap_lane, t);
           const K room = (K)(Bt - w);
