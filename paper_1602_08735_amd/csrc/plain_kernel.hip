@@ -455,29 +455,44 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         K nk = 0;
         const int ng = (CRIT == FF && (int64_t)w > ub) ? 0 : uniform((nlive + 255) >> 8);
         if constexpr (CRIT == FF) {
-          // groups in position order; the next group's keys are loaded while
-          // the four 64-bin rows of the current one are tested
-          K k[4], kn[4];
+          // the lowest position among the bins the item fits: a key with its
+          // halves swapped is pos << SH | room, so the least of those over
+          // the fitting bins names the first fit and its room
+          K best = ~(K)0;
           K kmax = 0;
-          if (ng > 0) load_group(keys, 0, lane, k);
-          for (int g = 0; g < ng; ++g) {
-            if (g + 1 < ng) load_group(keys, g + 1, lane, kn);
-            const uint64_t f0 = ballot(k[0] >= wk), f1 = ballot(k[1] >= wk);
-            const uint64_t f2 = ballot(k[2] >= wk), f3 = ballot(k[3] >= wk);
-            if (f0 | f1 | f2 | f3) {
-              const int j = f0 ? 0 : (f1 ? 1 : (f2 ? 2 : 3));
-              const uint64_t fm = f0 ? f0 : (f1 ? f1 : (f2 ? f2 : f3));
-              const int l = __builtin_ctzll(fm);
-              p = (g << 8) + (j << 6) + l;
-              const K kj = j == 0 ? k[0] : (j == 1 ? k[1] : (j == 2 ? k[2] : k[3]));
-              nk = readlane(kj, l) - wk;
-              break;
-            }
-            kmax = max(max(kmax, max(k[0], k[1])), max(k[2], k[3]));
+          auto cand = [&](K key) -> K {
+            const K sw = (key >> KT::SH) | (key << KT::SH);
+            return key >= wk ? sw : ~(K)0;
+          };
+          int g = 0;
+          for (; g + 1 < ng; g += 2) {
+            K k[4], k2[4];
+            load_group(keys, g, lane, k);
+            load_group(keys, g + 1, lane, k2);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) k[j] = kn[j];
+            for (int j = 0; j < 4; ++j) {
+              best = min(best, min(cand(k[j]), cand(k2[j])));
+              kmax = max(kmax, max(k[j], k2[j]));
+            }
           }
-          if (p < 0 && ng > 0) ub = (int64_t)(~wave_min(~kmax) >> KT::SH);
+          if (g < ng) {
+            K k[4];
+            load_group(keys, g, lane, k);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              best = min(best, cand(k[j]));
+              kmax = max(kmax, k[j]);
+            }
+          }
+          if (ng > 0) {
+            best = wave_min(best);
+            if (best != ~(K)0) {
+              p = (int)(best >> KT::SH);
+              nk = (((best & KT::POS) << KT::SH) | (K)p) - wk;
+            } else {
+            if (ng > 0) ub = (int64_t)(~wave_min(~kmax) >> KT::SH);
+            }
+          }
         } else {
           K best = ~(K)0;
           int g = 0;
