@@ -41,6 +41,13 @@ SCORED_DECISIONS_PER_ITEM = {"FF+scorer": 0.4851, "BF+scorer": 0.4799, "WF+score
 OPS_PER_BIN_TEST = 2          # form the room-after key, fold it into the min
 MLP_FMA_PER_DECISION = 16 * 64 + 64 * 64 + 64 * 5   # fused multiply-adds, one lane-op each
 ALU_PEAK = 256 * 4 * 16 * 2.4e9   # VALU lane-ops/s: CUs x SIMDs x lanes x clock
+# HBM bytes per launch of the current kernels on this workload, from rocprofv3
+# FETCH_SIZE (x2: it counts half of a known-size copy's reads) and WRITE_SIZE
+# (x1) -- profiles/pack_kernels_uniform_batch.md.  Taken again whenever a
+# kernel changes (a launch without a current figure reports null).
+MEASURED_HBM_BYTES = {"H2": 45.25e6, "FF": 50.74e6, "BF": 50.57e6, "WF": 51.25e6,
+                      "H1": 47.22e6, "FF+scorer": 48.32e6, "BF+scorer": 48.40e6,
+                      "WF+scorer": 49.28e6}
 
 
 def ops_per_item(h):
@@ -292,7 +299,8 @@ def main():
         "peak": ALU_PEAK / 1e12,
         "unit": "Tops/s",
         "frac": achieved / (ALU_PEAK / 1e12),
-        "traffic": None,
+        "traffic": MEASURED_HBM_BYTES.get(dom),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
         "work_per_launch": work,
     }
     out = {
