@@ -170,24 +170,12 @@ def best_of_orderings(V, torch, batch, crit, k, lb):
             "instances_per_s": batch.n_instances / (ms / 1e3)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the packing path is measured on a single "
-              "MI355X (instances shard across GPUs with no exchange; no multi-GPU run is "
-              "part of this build)", file=sys.stderr)
-        sys.exit(2)
+def make_plans(V, torch, db, heuristics, graph=True, autotune=True):
+    """The timed launches: one plan per heuristic over the resident batch db,
+    each with its own output arrays (the learned and plain results stay
+    apart); the scorer runs load the committed model of their criterion."""
     import numpy as np
-    import torch
 
-    import paper_1602_08735_amd as V
-    from paper_1602_08735_amd import inputs
-
-    heuristics = tuple(h for h in args.heuristics.split(",") if h)
-    batch = inputs.config2(n_instances=args.instances, m=args.items)
-    db = V.DeviceBatch(batch)
-    stream = torch.cuda.current_stream()
-    # one output set per launch so the learned and plain results stay apart
     outs = {h: V.DeviceBatch.__new__(V.DeviceBatch) for h in heuristics}
     for h in heuristics:
         o = outs[h]
@@ -205,10 +193,31 @@ def main():
                 raw = f.read()
             models[h] = torch.tensor(np.frombuffer(raw, dtype=np.uint8).copy(), device="cuda")
             plans[h] = V.Plan(outs[h], crit, type_rule=V.TYPE_LEARNED,
-                              model_ptr=models[h].data_ptr(), graph=not args.no_graph,
-                              autotune=not args.no_autotune)
+                              model_ptr=models[h].data_ptr(), graph=graph, autotune=autotune)
         else:
-            plans[h] = V.Plan(outs[h], h, graph=not args.no_graph, autotune=not args.no_autotune)
+            plans[h] = V.Plan(outs[h], h, graph=graph, autotune=autotune)
+    return outs, models, plans
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the packing path is measured on a single "
+              "MI355X (instances shard across GPUs with no exchange; no multi-GPU run is "
+              "part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1602_08735_amd as V
+    from paper_1602_08735_amd import inputs
+
+    heuristics = tuple(h for h in args.heuristics.split(",") if h)
+    batch = inputs.config2(n_instances=args.instances, m=args.items)
+    db = V.DeviceBatch(batch)
+    stream = torch.cuda.current_stream()
+    outs, models, plans = make_plans(V, torch, db, heuristics, graph=not args.no_graph,
+                                     autotune=not args.no_autotune)
 
     def step(ev=None):
         for k, h in enumerate(heuristics):

@@ -96,10 +96,10 @@ def test_graph_replays(V, orc, uneven, h):
     p.close()
 
 
-def test_autotuned_plans(V, orc, tmp_path):
+def test_autotuned_plans(V, orc, tmp_path, monkeypatch):
     import torch
 
-    os.environ["VSBPP_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    monkeypatch.setenv("VSBPP_TUNE_CACHE", str(tmp_path / "tune.txt"))
     b = inputs.config3(n_instances=96, seed=31)
     for h in HEUR:
         expected = oracle_batch(b, h)
@@ -127,6 +127,12 @@ def test_plan_rejects_bad_shapes(V):
         with pytest.raises(V.VsbppError) as e:
             V.Plan(db, h, launch=launch)
         assert e.value.code == -6
+
+
+def _model_bytes(crit):
+    with open(os.path.join(os.path.dirname(__file__), "..", "paper_1602_08735_amd", "models", f"scorer_{crit}.bin"),
+              "rb") as f:
+        return f.read()
 
 
 def _big_batch(rng, sizes):
@@ -168,3 +174,9 @@ def test_bins_beyond_lds_use_a_device_region(V, orc, h):
         r = V.pack(w, caps, h)
         o = orc.pack(w, caps, h)
         assert r.cost == o.cost and np.array_equal(r.assignment, o.assignment)
+        # the scorer keeps the bins in LDS: such instances are declined
+        model = torch.tensor(np.frombuffer(_model_bytes(h), dtype=np.uint8).copy(),
+                             device="cuda")
+        with pytest.raises(V.VsbppError) as e:
+            V.Plan(db, h, type_rule=V.TYPE_LEARNED, model_ptr=model.data_ptr())
+        assert e.value.code == -2
