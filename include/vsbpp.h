@@ -232,6 +232,32 @@ int32_t vsbpp_plan_launch(const vsbpp_plan* plan, vsbpp_launch* out);
 /* Releases the plan, its workspace and graph (after outstanding runs). */
 void vsbpp_plan_destroy(vsbpp_plan* plan);
 
+/* Exact optimum of every instance of a device-resident batch with at most
+ * 12 items per instance (batch->max_items <= 12), for measuring heuristic
+ * and learned packings against the optimum.  The cost of a packing is the
+ * sum of the capacities of its bins (Section 2), so a bin holding a set of
+ * items costs the smallest capacity that holds their total and the optimum
+ * is the cheapest partition of the items into such sets.  The call evaluates
+ * it exactly, by dynamic programming over the subsets of the items.
+ *   batch    the CSR inputs and bounds of vsbpp_pack_batch (order and seeds
+ *            are ignored); every instance needs 1 <= m_i <= 12
+ *   outputs  d_cost[i]   the optimum cost;
+ *            d_nbins[i]  the bins of one optimal packing, or a negative
+ *                        VSBPP_E_* code for an instance that fails the checks
+ *                        of vsbpp_pack_batch or has more than max_items or
+ *                        12 items (its other outputs are then unspecified);
+ *            d_assignment / d_bin_types  that packing, in the layout of
+ *                        vsbpp_pack_batch.  Its bins are ordered by their
+ *                        lowest item and each has the smallest type that
+ *                        holds its load.  Where several packings are optimal
+ *                        it is the one whose first bin, as a bit mask of
+ *                        items, is smallest, then the same rule for the
+ *                        items left.
+ * Asynchronous on hip_stream, no device allocation (graph-capturable).
+ * Returns VSBPP_OK, VSBPP_E_NULL, VSBPP_E_SIZE (max_items outside 1..12,
+ * max_types outside 1..16, max_capacity < 1) or VSBPP_E_DEVICE. */
+int32_t vsbpp_exact_batch(const vsbpp_batch* batch, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Learned bin-type scorer.                                                  */
 /*                                                                            */

@@ -35,7 +35,7 @@ EXPORTS = (
     "vsbpp_pack_batch_ex", "vsbpp_rollout_labels", "vsbpp_trainer_create",
     "vsbpp_trainer_step", "vsbpp_trainer_gradient", "vsbpp_trainer_device_model",
     "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
-    "vsbpp_plan_create_ex",
+    "vsbpp_plan_create_ex", "vsbpp_exact_batch",
 )
 
 
@@ -376,6 +376,8 @@ def _learn_lib():
                                            ctypes.POINTER(vp)]
         L.vsbpp_lower_bounds.restype = i32
         L.vsbpp_lower_bounds.argtypes = [i32, vp, vp, vp, vp, vp, vp]
+        L.vsbpp_exact_batch.argtypes = [ctypes.POINTER(_BatchDesc), vp]
+        L.vsbpp_exact_batch.restype = i32
         L._learn_ready = True
     return L
 
@@ -435,6 +437,18 @@ def lower_bounds(db: DeviceBatch, out, stream=None):
                                          out.data_ptr(), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise VsbppError(rc, "vsbpp_lower_bounds")
+
+
+def exact_batch(db: DeviceBatch, stream=None) -> None:
+    """vsbpp_exact_batch: the optimum cost of every instance (at most 12
+    items each) and one optimal packing, into db's outputs."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    d = _desc(db, use_order=False, use_seeds=False)
+    rc = _learn_lib().vsbpp_exact_batch(ctypes.byref(d), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_exact_batch")
 
 
 class Trainer:

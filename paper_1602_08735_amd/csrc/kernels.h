@@ -93,6 +93,14 @@ hipError_t launch_bounds(int32_t num, const int32_t* w, const int64_t* item_off,
                          const int32_t* caps, const int32_t* cap_off, int64_t* out,
                          hipStream_t s);
 
+// exact optimum of instances with at most 12 items (subset dynamic
+// programme, one workgroup of `block` threads (128..512, a multiple of 64)
+// per instance; grid = 0: one workgroup per instance, else a static stride)
+constexpr int kExactMaxItems = 12;
+bool exact_wide(const BatchArgs& a);
+hipError_t launch_exact(const BatchArgs& a, int block, int grid, hipStream_t s);
+int exact_blocks_per_cu(const BatchArgs& a, int block);
+
 // scheduling helpers
 hipError_t launch_queue_reset(int32_t* queue, hipStream_t s);
 // instances sorted by decreasing item count (ties by index); num <= kLptMax

@@ -495,6 +495,43 @@ int32_t vsbpp_best_of(const int64_t* d_cost, int32_t num, int64_t* d_out, void* 
   return VSBPP_OK;
 }
 
+int32_t vsbpp_exact_batch(const vsbpp_batch* b, void* hip_stream) {
+  if (!b) return VSBPP_E_NULL;
+  if (b->num_instances < 0) return VSBPP_E_SIZE;
+  if (b->num_instances == 0) return VSBPP_OK;
+  if (!b->weights || !b->item_off || !b->capacities || !b->cap_off || !b->assignment ||
+      !b->bin_types || !b->nbins || !b->cost)
+    return VSBPP_E_NULL;
+  if (b->max_items < 1 || b->max_items > vsbpp::kExactMaxItems || b->max_types < 1 ||
+      b->max_types > vsbpp::kMaxTypes || b->max_capacity < 1)
+    return VSBPP_E_SIZE;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!device_ok_locked()) return VSBPP_E_DEVICE;
+  }
+  BatchArgs a{};
+  a.w = b->weights;
+  a.item_off = b->item_off;
+  a.caps = b->capacities;
+  a.cap_off = b->cap_off;
+  a.assign = b->assignment;
+  a.types = b->bin_types;
+  a.nbins = b->nbins;
+  a.cost = b->cost;
+  a.num = b->num_instances;
+  a.max_items = b->max_items;
+  a.max_cap = b->max_capacity;
+  a.max_types = b->max_types;
+  constexpr int kBlock = 256;
+  const int grid = vsbpp::exact_blocks_per_cu(a, kBlock) * vsbpp::device_info().cus;
+  const hipError_t e = vsbpp::launch_exact(a, kBlock, grid, (hipStream_t)hip_stream);
+  if (e != hipSuccess) {
+    vsbpp::set_last_error("vsbpp_exact_batch", e);
+    return VSBPP_E_DEVICE;
+  }
+  return VSBPP_OK;
+}
+
 }  // extern "C"
 
 namespace vsbpp {

@@ -122,3 +122,22 @@ def test_plan_host_checks(V):
         assert out.value is None
     assert L.vsbpp_plan_run(None, None) == -1
     L.vsbpp_plan_destroy(None)
+
+
+def test_exact_batch_host_checks(V):
+    L = V._learn_lib()
+    assert L.vsbpp_exact_batch(None, None) == -1
+    d = V._BatchDesc()
+    d.num_instances = 0
+    assert L.vsbpp_exact_batch(ctypes.byref(d), None) == 0
+    d.num_instances = 3
+    assert L.vsbpp_exact_batch(ctypes.byref(d), None) == -1
+    for f in ("weights", "item_off", "capacities", "cap_off", "assignment", "bin_types",
+              "nbins", "cost"):
+        setattr(d, f, 16)
+    for mi, nt, mc in ((13, 3, 100), (0, 3, 100), (12, 17, 100), (12, 0, 100), (12, 3, 0)):
+        d.max_items, d.max_types, d.max_capacity = mi, nt, mc
+        assert L.vsbpp_exact_batch(ctypes.byref(d), None) == -2, (mi, nt, mc)
+    if not V.device_ok():
+        d.max_items, d.max_types, d.max_capacity = 12, 3, 100
+        assert L.vsbpp_exact_batch(ctypes.byref(d), None) == -7
