@@ -50,6 +50,20 @@ MEASURED_HBM_BYTES = {"H2": 45.25e6, "FF": 50.74e6, "BF": 50.57e6, "WF": 51.25e6
                       "WF+scorer": 49.28e6}
 
 
+# Exact solver leg (outside the step): instances of the uniform distribution
+# small enough to solve exactly.  The dynamic programme evaluates
+# (3^m - 1) / 2 candidate blocks per instance (every subset S with every
+# block T of S that holds the lowest item of S), two ops each (add the block
+# cost, fold into the minimum) and two LDS key reads each.
+EXACT_ITEMS = 12
+EXACT_OPS_PER_CANDIDATE = 2
+LDS_PEAK = 256 * 128 * 2.4e9      # bytes/s: CUs x 128 B/clk x clock
+
+
+def exact_candidates(m):
+    return (3 ** m - 1) // 2
+
+
 def ops_per_item(h):
     """Algorithmic VALU lane-ops per item placed by launch h."""
     return (OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[h]
@@ -66,6 +80,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--heuristics", default=",".join(HEURISTICS + LEARNED))
+    ap.add_argument("--exact-instances", type=int, default=16384,
+                    help="instances of the exact-solver leg (0 skips it)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -130,6 +146,92 @@ def cpu_baseline(batch, heuristics, n_sample):
         "sample": f"{len(idx)} of {batch.n_instances} instances x {len(heuristics)} heuristics "
                   f"({items} item placements), {dt:.2f} s wall on {cores} threads",
     }, per_item, scored
+
+
+def exact_leg(V, torch, n_inst, steps, warmup, cpu_sample):
+    """Times the exact solver on n_inst instances of m = EXACT_ITEMS items and
+    measures every launch of the step against the optimum of the same
+    instances."""
+    import numpy as np
+
+    from paper_1602_08735_amd import inputs
+
+    m = EXACT_ITEMS
+    b = inputs.small_uniform(n_inst, m)
+    db = V.DeviceBatch(b)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        V.exact_batch(db)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        V.exact_batch(db)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nb = db.nbins.cpu().numpy()
+    if (nb < 1).any():
+        raise RuntimeError("exact solver: device reported instance errors")
+    opt = db.cost.cpu().numpy().astype(np.float64)
+    cand = exact_candidates(m) * n_inst
+    ops = EXACT_OPS_PER_CANDIDATE * cand
+    achieved = ops / (ms / 1e3) / 1e12
+    lds_bytes = 2 * 4 * cand     # two 32-bit key reads per candidate
+    # every launch of the step on the same instances, against the optimum
+    gap = {}
+    outs, models, plans = make_plans(V, torch, db, HEURISTICS + LEARNED, graph=False,
+                                     autotune=False)
+    for h, p in plans.items():
+        p.run(stream)
+        torch.cuda.synchronize()
+        c = outs[h].cost.cpu().numpy().astype(np.float64)
+        gap[h] = {"mean_cost_over_opt": float((c / opt).mean()),
+                  "optimal_share": float((c == opt).mean())}
+        p.close()
+    out = {
+        "workload": f"{n_inst} instances x {m} items, 5 bin types (B_1=200, 4 distinct in "
+                    "[100,199]), w~U[1,200]",
+        "ms": ms,
+        "instances_per_s": n_inst / (ms / 1e3),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "exact subset DP (k_exact, 32-bit keys)",
+            "achieved": achieved,
+            "peak": ALU_PEAK / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / (ALU_PEAK / 1e12),
+            "work_per_launch": f"({EXACT_OPS_PER_CANDIDATE} ops x (3^{m}-1)/2 candidate blocks) "
+                               f"per instance x {n_inst} instances",
+            "lds_bytes_per_s": lds_bytes / (ms / 1e3),
+            "lds_frac": lds_bytes / (ms / 1e3) / LDS_PEAK,
+        },
+        "heuristics_vs_optimum": gap,
+    }
+    if cpu_sample > 0:
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+
+        oracle.build()
+        idx = list(range(min(cpu_sample, n_inst)))
+        cores = max(1, min(16, os.cpu_count() or 1))
+
+        def one(i):
+            w, caps, _ = b.instance(i)
+            return oracle.opt_subset_dp(w, caps)
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            got = list(ex.map(one, idx))
+        dt = time.perf_counter() - t0
+        if any(g != int(opt[i]) for g, i in zip(got, idx)):
+            raise RuntimeError("exact solver: optimum differs from the oracle")
+        out["cpu_baseline"] = {"value": len(idx) / dt, "unit": "instances/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{len(idx)} of {n_inst} instances (subset DP), "
+                                         f"{dt:.2f} s wall on {cores} threads"}
+    return out
 
 
 def best_of_orderings(V, torch, batch, crit, k, lb):
@@ -342,6 +444,9 @@ def main():
         "learned_vs_plain": learned_cmp,
         "launch_shapes": {h: plans[h].launch() for h in heuristics},
     }
+    if args.exact_instances > 0:
+        out["exact_solver"] = exact_leg(V, torch, args.exact_instances, args.steps, args.warmup,
+                                        0 if args.no_cpu_baseline else args.exact_instances)
     if not args.no_cpu_baseline:
         cb, per_item, scored = cpu_baseline(batch, heuristics, args.cpu_sample)
         out["cpu_baseline"] = cb

@@ -522,7 +522,7 @@ int32_t vsbpp_exact_batch(const vsbpp_batch* b, void* hip_stream) {
   a.max_items = b->max_items;
   a.max_cap = b->max_capacity;
   a.max_types = b->max_types;
-  constexpr int kBlock = 256;
+  constexpr int kBlock = 512;
   const int grid = vsbpp::exact_blocks_per_cu(a, kBlock) * vsbpp::device_info().cus;
   const hipError_t e = vsbpp::launch_exact(a, kBlock, grid, (hipStream_t)hip_stream);
   if (e != hipSuccess) {

@@ -212,6 +212,20 @@ def random_small(rng: np.random.Generator, m_max: int = 10, n_max: int = 4, b1_m
     return w, caps
 
 
+def small_uniform(n_instances: int = 16384, m: int = 12, seed: int = 12) -> Batch:
+    """Instances of the uniform-batch distribution small enough to solve
+    exactly: m items (default 12), B_1 = 200 plus four distinct capacities
+    from [100,199], weights uniform in [1,200]."""
+    rng = np.random.default_rng(seed)
+    ws, cs = [], []
+    for _ in range(n_instances):
+        w, c = c2_instance(rng, m)
+        ws.append(w)
+        cs.append(c)
+    seeds = np.arange(n_instances, dtype=np.uint64) + np.uint64(seed) * np.uint64(1 << 32)
+    return make_batch(ws, cs, None, seeds, {"workload": "small-uniform", "m": m})
+
+
 def random_batch(rng: np.random.Generator, n_instances: int, m_lo: int, m_hi: int,
                  n_lo: int = 1, n_hi: int = 7, b1_hi: int = 1000) -> Batch:
     """Random mixed batch for parity tests (ragged sizes, any n, any B_1)."""
