@@ -57,6 +57,9 @@ MEASURED_HBM_BYTES = {"H2": 45.25e6, "FF": 50.74e6, "BF": 50.57e6, "WF": 51.25e6
 # cost, fold into the minimum) and two LDS key reads each.
 EXACT_ITEMS = 12
 EXACT_OPS_PER_CANDIDATE = 2
+# HBM bytes per launch of the exact kernel on 16384 instances (rocprofv3,
+# profiles/exact_solver_m12.md); null for another batch size
+EXACT_HBM_BYTES_16384 = 14.33e6
 LDS_PEAK = 256 * 128 * 2.4e9      # bytes/s: CUs x 128 B/clk x clock
 
 
@@ -178,6 +181,7 @@ def exact_leg(V, torch, n_inst, steps, warmup, cpu_sample):
     ops = EXACT_OPS_PER_CANDIDATE * cand
     achieved = ops / (ms / 1e3) / 1e12
     lds_bytes = 2 * 4 * cand     # two 32-bit key reads per candidate
+    hbm = EXACT_HBM_BYTES_16384 if n_inst == 16384 else None
     # every launch of the step on the same instances, against the optimum
     gap = {}
     outs, models, plans = make_plans(V, torch, db, HEURISTICS + LEARNED, graph=False,
@@ -195,16 +199,20 @@ def exact_leg(V, torch, n_inst, steps, warmup, cpu_sample):
         "ms": ms,
         "instances_per_s": n_inst / (ms / 1e3),
         "roofline": {
-            "bound": "alu",
+            "bound": "lds",
             "kernel": "exact subset DP (k_exact, 32-bit keys)",
-            "achieved": achieved,
-            "peak": ALU_PEAK / 1e12,
-            "unit": "Tops/s",
-            "frac": achieved / (ALU_PEAK / 1e12),
-            "work_per_launch": f"({EXACT_OPS_PER_CANDIDATE} ops x (3^{m}-1)/2 candidate blocks) "
-                               f"per instance x {n_inst} instances",
-            "lds_bytes_per_s": lds_bytes / (ms / 1e3),
-            "lds_frac": lds_bytes / (ms / 1e3) / LDS_PEAK,
+            "achieved": lds_bytes / (ms / 1e3) / 1e12,
+            "peak": LDS_PEAK / 1e12,
+            "unit": "TB/s",
+            "frac": lds_bytes / (ms / 1e3) / LDS_PEAK,
+            "traffic": hbm,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
+            "work_per_launch": f"(3^{m}-1)/2 candidate blocks per instance x {n_inst} "
+                               "instances, each 2 LDS key reads of 4 B and "
+                               f"{EXACT_OPS_PER_CANDIDATE} ops",
+            "alu_achieved": achieved,
+            "alu_peak": ALU_PEAK / 1e12,
+            "alu_frac": achieved / (ALU_PEAK / 1e12),
         },
         "heuristics_vs_optimum": gap,
     }
