@@ -82,6 +82,7 @@ typedef struct {
   int32_t type;
   int64_t load;
   int32_t divided;
+  int32_t closed;  /* bounded plain runs: the bin takes no more items */
 } obin;
 
 typedef struct {
@@ -99,6 +100,7 @@ static void pk_push(opacker* p, int32_t type) {
   p->b[p->nb].type = type;
   p->b[p->nb].load = 0;
   p->b[p->nb].divided = 0;
+  p->b[p->nb].closed = 0;
   p->nb++;
 }
 
@@ -118,6 +120,12 @@ static int32_t open_type(const int32_t* caps, int32_t n, int32_t w, int32_t rule
  *   BF: least room left after placing; ties -> lowest index.
  *   WF: most room left after placing; ties -> lowest index.
  * No candidate: open a bin (type per open_type).
+ * Bounded runs (active_limit > 0, plain heuristics only): only bins that are
+ * not closed are candidates, and a bin about to open while active_limit bins
+ * are open first closes the fullest open bin (least room; lowest index on
+ * ties).  Section 1 says Best Fit keeps a fixed number of bins active but
+ * gives no closing rule; this one is the Best-k-Fit rule of bounded-space
+ * bin packing (Csirik & Johnson, Algorithmica 2001).
  * Rule 5 (when enabled): a bin whose load reaches half its capacity and that
  * has not divided yet divides once, adding an empty bin of its type.
  * `suffix_min` is the smallest weight among this item and all later items of
@@ -125,11 +133,12 @@ static int32_t open_type(const int32_t* caps, int32_t n, int32_t w, int32_t rule
 typedef int32_t (*type_chooser)(void* ctx, int32_t w);
 
 static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
-                     int32_t crit, int32_t rule5, int32_t type_rule,
+                     int32_t crit, int32_t rule5, int32_t type_rule, int32_t active_limit,
                      int64_t suffix_min, orc_stats* st, type_chooser choose, void* cctx) {
   int32_t best = -1;
   int64_t best_after = 0;
   for (int32_t b = 0; b < p->nb; ++b) {
+    if (p->b[b].closed) continue;
     int64_t room = (int64_t)caps[p->b[b].type] - p->b[b].load;
     if (st) {
       st->bin_tests++;
@@ -147,6 +156,20 @@ static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
     }
   }
   if (best < 0) {
+    if (active_limit > 0) {
+      int32_t open = 0, fullest = -1;
+      int64_t least = 0;
+      for (int32_t b = 0; b < p->nb; ++b) {
+        if (p->b[b].closed) continue;
+        ++open;
+        const int64_t room = (int64_t)caps[p->b[b].type] - p->b[b].load;
+        if (fullest < 0 || room < least) {
+          fullest = b;
+          least = room;
+        }
+      }
+      if (open >= active_limit) p->b[fullest].closed = 1;
+    }
     pk_push(p, choose ? choose(cctx, w) : open_type(caps, n, w, type_rule));
     best = p->nb - 1;
     if (st) st->new_bins++;
@@ -218,6 +241,7 @@ static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_
          heuristic > ORC_WF))
       return ORC_E_OPTION;
     if (o->force_crit < -1 || o->force_crit > ORC_WF) return ORC_E_OPTION;
+    if (o->active_limit < 0 || (o->active_limit > 0 && heuristic > ORC_WF)) return ORC_E_OPTION;
     if (o->order) {
       /* must be a permutation of [0,m) */
       char* seen = (char*)calloc((size_t)m, 1);
@@ -403,7 +427,8 @@ static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32
     c.smin_after = q + 1 < m ? smin[q + 1] : -1;
     c.nb = p.nb;
     const int32_t nb_before = p.nb;
-    const int32_t b = place(&p, caps, n, wq, crit, 0, o->type_rule, smin[q], st, plain_choose, &c);
+    const int32_t b = place(&p, caps, n, wq, crit, 0, o->type_rule, o->active_limit, smin[q], st,
+                              plain_choose, &c);
     local[q] = b;
     const int64_t room = (int64_t)caps[p.b[b].type] - p.b[b].load;
     if (b != nb_before) c.hist[room_bucket(room + wq, caps[0])]--;
@@ -430,7 +455,7 @@ int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int3
   orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count};
+  orc_opts o = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label = -1;
   if (rc >= 0 && d < count) {
@@ -442,7 +467,7 @@ int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int3
       if (!((feasible >> k1) & 1u)) continue;
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < n; ++k2) {
-        orc_opts f = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL};
+        orc_opts f = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }
@@ -494,7 +519,7 @@ static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
     for (int32_t t = 0; t < k; ++t) {
       int32_t c = o->force_crit >= 0 ? o->force_crit
                                      : orc_criterion(ck, (uint64_t)(q0 + t));
-      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, smin[t], st, NULL, NULL);
+      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL);
     }
     base += emit_packer(&p, caps, items, local, k, base, assign, types, cost);
     pk_free(&p);
@@ -564,7 +589,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
         int32_t c = o->force_crit >= 0
                         ? o->force_crit
                         : orc_criterion(ck, (uint64_t)(((int64_t)I * P + r) * S + t));
-        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, smin[t], st, NULL, NULL);
+        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL);
       }
       int64_t c = packer_cost(&p, caps);
       if (best_r < 0 || c < best_cost) {
@@ -584,7 +609,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
                       ? o->force_crit
                       : orc_criterion(ck, (uint64_t)(((int64_t)I * P + best_r) * S + t));
       placed_items[t] = items[order[t]];
-      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, NULL, NULL, NULL);
+      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, 0, NULL, NULL, NULL);
     }
     base += emit_packer(&p, caps, placed_items, local, k, base, assign, types, cost);
     pk_free(&p);
@@ -596,7 +621,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
 int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                  int32_t heuristic, const orc_opts* opt, int32_t* assign,
                  int32_t* types, int64_t* cost, orc_stats* stats) {
-  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL};
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0};
   const orc_opts* o = opt ? opt : &def;
   if (!assign || !types || !cost) return ORC_E_NULL;
   int32_t rc = validate(w, m, caps, n, heuristic, o);
@@ -631,7 +656,7 @@ int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
     for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
   for (int32_t t = 0; t < m; ++t) {
     items[t] = t;
-    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, NULL, NULL, NULL);
+    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, 0, NULL, NULL, NULL);
   }
   *cost = 0;
   int32_t nb = emit_packer(&p, caps, items, local, m, 0, assign, types, cost);

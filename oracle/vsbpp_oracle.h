@@ -70,6 +70,8 @@ typedef struct {
   orc_decision* trace;    /* optional: receives the run's decisions        */
   int32_t trace_cap;      /* capacity of trace                             */
   int32_t* trace_count;   /* number of decisions of the run                */
+  int32_t active_limit;   /* plain FF/BF/WF: at most this many bins open at
+                             once (0: no limit); see run_plain               */
 } orc_opts;
 
 typedef struct {

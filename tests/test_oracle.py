@@ -320,3 +320,86 @@ def test_error_codes(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.pack([1, 2], [10, 5], "H1", order=[0, 0])
     assert e.value.code == -6
+
+
+# ---------------------------------------------------------------------------
+# Bounded active bins (plain heuristics): at most K bins open, the fullest
+# closes when a bin must open while K are open.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ex", ["F", "G", "H"])
+def test_bounded_hand_examples(orc, ex):
+    e = golden("bounded_examples.json")[ex]
+    for h in ("FF", "BF", "WF"):
+        if h not in e:
+            continue
+        r = orc.pack(e["w"], e["caps"], h, active_limit=e["K"])
+        assert r.assignment.tolist() == e[h]["assignment"], h
+        assert r.bin_types.tolist() == e[h]["types"], h
+        assert r.cost == e[h]["cost"], h
+        assert orc.pack(e["w"], e["caps"], h).assignment.tolist() == e["unbounded"][h], h
+
+
+def _next_fit(w, caps):
+    """Textbook Next Fit with the smallest fitting type for each new bin."""
+    asg, types, room = [], [], -1
+    for x in w:
+        if x > room:
+            k = max(i for i in range(len(caps)) if caps[i] >= x)
+            types.append(k)
+            room = int(caps[k])
+        room -= int(x)
+        asg.append(len(types) - 1)
+    return asg, types
+
+
+def test_bounded_one_bin_is_next_fit(orc):
+    """With one active bin every criterion reduces to Next Fit."""
+    rng = np.random.default_rng(77)
+    for _ in range(60):
+        n = int(rng.integers(1, 6))
+        b1 = int(rng.integers(n + 1, 400))
+        caps = np.concatenate([[b1], inputs._distinct_desc(rng, 1, b1 - 1, n - 1)])
+        w = rng.integers(1, b1 + 1, size=int(rng.integers(1, 200)))
+        asg, types = _next_fit(w, caps)
+        for h in ("FF", "BF", "WF"):
+            r = orc.pack(w, caps, h, active_limit=1)
+            assert r.assignment.tolist() == asg, h
+            assert r.bin_types.tolist() == types, h
+
+
+def test_bounded_large_limit_is_unbounded(orc):
+    """A limit no smaller than the bins a run opens changes nothing."""
+    rng = np.random.default_rng(78)
+    for _ in range(40):
+        b = inputs.random_batch(rng, 1, 1, 300)
+        w, caps, _ = b.instance(0)
+        for h in ("FF", "BF", "WF"):
+            for rule in (orc.TYPE_SMALLEST_FIT, orc.TYPE_LARGEST):
+                u = orc.pack(w, caps, h, type_rule=rule)
+                for K in (u.nbins, u.nbins + 5, len(w)):
+                    r = orc.pack(w, caps, h, type_rule=rule, active_limit=K)
+                    assert r.assignment.tolist() == u.assignment.tolist(), (h, K)
+                    assert r.cost == u.cost
+
+
+def test_bounded_items_above_half(orc):
+    """Items heavier than B_1/2 never share a bin, whatever the limit."""
+    rng = np.random.default_rng(79)
+    caps = [100, 80, 60]
+    w = rng.integers(51, 101, size=50)
+    for h in ("FF", "BF", "WF"):
+        for K in (1, 2, 7):
+            r = orc.pack(w, caps, h, active_limit=K)
+            assert r.assignment.tolist() == list(range(50))
+            assert r.cost == orc.lb_big(w, caps)
+
+
+def test_bounded_option_checks(orc):
+    with pytest.raises(orc.OracleError) as e:
+        orc.pack([1, 2], [10], "BF", active_limit=-1)
+    assert e.value.code == -6
+    for h in ("H1", "H2"):
+        with pytest.raises(orc.OracleError) as e:
+            orc.pack([1, 2], [10], h, active_limit=3)
+        assert e.value.code == -6
