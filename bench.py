@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--heuristics", default=",".join(HEURISTICS + LEARNED))
+    ap.add_argument("--active-limit", type=int, default=16,
+                    help="open-bin bound of the bounded FF/BF/WF leg (0 skips it)")
     ap.add_argument("--exact-instances", type=int, default=16384,
                     help="instances of the exact-solver leg (0 skips it)")
     ap.add_argument("--no-graph", action="store_true")
@@ -239,6 +241,41 @@ def exact_leg(V, torch, n_inst, steps, warmup, cpu_sample):
                                "kind": "oracle",
                                "sample": f"{len(idx)} of {n_inst} instances (subset DP), "
                                          f"{dt:.2f} s wall on {cores} threads"}
+    return out
+
+
+def bounded_leg(V, torch, db, lb, limit, steps, warmup):
+    """Plain FF/BF/WF with at most `limit` bins open (the fullest closes),
+    as autotuned graph plans on the step's batch: time and cost/LB."""
+    import numpy as np
+
+    stream = torch.cuda.current_stream()
+    out = {}
+    for crit in ("FF", "BF", "WF"):
+        o = V.DeviceBatch.__new__(V.DeviceBatch)
+        o.__dict__.update(db.__dict__)
+        o.assignment = torch.empty_like(db.assignment)
+        o.bin_types = torch.empty_like(db.bin_types)
+        o.nbins = torch.empty_like(db.nbins)
+        o.cost = torch.empty_like(db.cost)
+        p = V.Plan(o, crit, graph=True, autotune=True, active_limit=limit)
+        for _ in range(warmup):
+            p.run(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            p.run(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        if (o.nbins.cpu().numpy() < 1).any():
+            raise RuntimeError(f"bounded {crit}: device reported instance errors")
+        cost = o.cost.cpu().numpy().astype(np.float64)
+        out[f"{crit} K={limit}"] = {"ms": ms, "items_per_s": db.total / (ms / 1e3),
+                                    "mean_cost_over_lb": float((cost / lb).mean()),
+                                    "launch": p.launch()}
+        p.close()
     return out
 
 
@@ -452,6 +489,9 @@ def main():
         "learned_vs_plain": learned_cmp,
         "launch_shapes": {h: plans[h].launch() for h in heuristics},
     }
+    if args.active_limit > 0:
+        out["bounded_active_bins"] = bounded_leg(V, torch, db, lb, args.active_limit,
+                                                 args.steps, args.warmup)
     if args.exact_instances > 0:
         out["exact_solver"] = exact_leg(V, torch, args.exact_instances, args.steps, args.warmup,
                                         0 if args.no_cpu_baseline else args.exact_instances)

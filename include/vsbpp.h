@@ -96,6 +96,16 @@ typedef struct vsbpp_options {
                                place of Rule 1's drawn permutation.  Host
                                pointer for vsbpp_pack_ex; ignored by
                                vsbpp_pack_batch (which takes d_order).         */
+  int32_t active_limit;     /* plain FF/BF/WF: at most this many bins open at
+                               once (0, the default: no limit).  Section 1
+                               has Best Fit keep a fixed number of bins
+                               active; when a bin must open while this many
+                               are open, the fullest open bin (least room,
+                               lowest index on ties) closes and takes no more
+                               items.  Nonzero with H1/H2: VSBPP_E_OPTION.
+                               (Appended last: callers built against the
+                               shorter struct keep working through
+                               struct_size.)                                   */
 } vsbpp_options;
 
 void vsbpp_options_init(vsbpp_options* opt);

@@ -57,6 +57,7 @@ class Options(ctypes.Structure):
         ("type_rule", ctypes.c_int32),
         ("force_criterion", ctypes.c_int32),
         ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("active_limit", ctypes.c_int32),
     ]
 
 
@@ -96,7 +97,7 @@ def lib():
 
 
 def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT,
-            force_crit: int = -1) -> Options:
+            force_crit: int = -1, active_limit: int = 0) -> Options:
     o = Options()
     lib().vsbpp_options_init(ctypes.byref(o))
     o.seed = seed & (2**64 - 1)
@@ -104,6 +105,7 @@ def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMAL
     o.h2_subset_size = s2
     o.type_rule = type_rule
     o.force_criterion = force_crit
+    o.active_limit = active_limit
     return o
 
 
@@ -128,7 +130,8 @@ def _heur(h) -> int:
 
 
 def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
-         type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, order=None) -> Packing:
+         type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, order=None,
+         active_limit: int = 0) -> Packing:
     """One instance through vsbpp_pack_ex (host arrays, synchronous)."""
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.int32))
     c = np.ascontiguousarray(np.asarray(caps, dtype=np.int32))
@@ -136,7 +139,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     a = np.zeros(max(m, 1), dtype=np.int32)
     t = np.zeros(max(m, 1), dtype=np.int32)
     cost = ctypes.c_int64(0)
-    o = options(seed, s1, s2, type_rule, force_crit)
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit)
     ordv = None
     if order is not None:
         ordv = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
@@ -180,13 +183,13 @@ class DeviceBatch:
 
 def pack_batch(db: DeviceBatch, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
                type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, stream=None,
-               use_order: bool = True, use_seeds: bool = True) -> None:
+               use_order: bool = True, use_seeds: bool = True, active_limit: int = 0) -> None:
     """Launches vsbpp_pack_batch on the given torch stream (default: current).
     Results land in db.assignment / db.bin_types / db.nbins / db.cost."""
     import torch
 
     s = stream if stream is not None else torch.cuda.current_stream()
-    o = options(seed, s1, s2, type_rule, force_crit)
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit)
     ptr = lambda x: None if x is None else x.data_ptr()
     rc = lib().vsbpp_pack_batch(
         db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
@@ -256,7 +259,8 @@ class Plan:
     def __init__(self, db: DeviceBatch, heuristic, *, launch: dict | None = None,
                  graph: bool = False, autotune: bool = False, seed: int = 0, s1: int = 10,
                  s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
-                 use_order: bool = True, use_seeds: bool = True, model_ptr=None):
+                 use_order: bool = True, use_seeds: bool = True, model_ptr=None,
+                 active_limit: int = 0):
         L = _plan_lib()
         ptr = lambda x: None if x is None else x.data_ptr()
         self.db = db
@@ -265,7 +269,7 @@ class Plan:
             ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
             db.max_items, db.max_types, db.max_cap,
             ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
-        o = options(seed, s1, s2, type_rule, force_crit)
+        o = options(seed, s1, s2, type_rule, force_crit, active_limit)
         lp = None
         if launch is not None:
             lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
@@ -394,7 +398,8 @@ def _desc(db: DeviceBatch, use_order=True, use_seeds=True, outputs=True, num=Non
 
 def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force=None,
                   features=None, info=None, nbins=None, cost=None, seed: int = 0,
-                  type_rule: int = TYPE_SMALLEST_FIT, stream=None) -> None:
+                  type_rule: int = TYPE_SMALLEST_FIT, stream=None,
+                  active_limit: int = 0) -> None:
     """vsbpp_pack_batch_ex.  With `src` (int32 tensor [E]) the batch has E
     entries reading instance src[e]; nbins/cost then receive E results (pass
     tensors of size E)."""
@@ -409,7 +414,7 @@ def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force
     if cost is not None:
         d.cost = cost.data_ptr()
     dec = _Decisions(ptr(src), ptr(force), ptr(features), ptr(info))
-    o = options(seed, type_rule=type_rule)
+    o = options(seed, type_rule=type_rule, active_limit=active_limit)
     rc = L.vsbpp_pack_batch_ex(ctypes.byref(d), _heur(heuristic), ctypes.byref(o), model_ptr,
                                ctypes.byref(dec), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:

@@ -24,9 +24,10 @@
 // ones, so one layer is one parallel step.  In layer k each subset has
 // 2^(k-1) candidate blocks; a group of g lanes shares a subset (g = 2^(k-6)
 // clamped to [1,64], so each lane takes 32 candidates when there are that
-// many: the per-subset set-up is then small next to the candidates).  The lane fixes the lowest log2(g) free items of the block by
-// its index and walks the subsets of the other free items in Gray-code
-// order, one item toggled per step.
+// many: the per-subset set-up is then small next to the candidates).  The
+// lane fixes the lowest log2(g) free items of the block by its index and
+// walks the subsets of the other free items in Gray-code order, one item
+// toggled per step.
 //
 // P(X) = X ^ (X >> 6) is a bijection of 12-bit masks that folds the high
 // items into the low address bits, so the lanes of a group, which differ in

@@ -32,6 +32,7 @@ struct BatchArgs {
   int32_t max_types;        // bound on n guaranteed by the caller
   int32_t type_rule;        // 0 smallest fit, 1 largest
   int32_t force_crit;       // -1 or 0/1/2 (H1/H2 only)
+  int32_t active_limit;     // plain FF/BF/WF: bins open at once (0: no limit)
   int32_t s1;               // H1 items per sublist
   int32_t s2;               // H2 subset size
   int32_t slots;            // plain kernel: LDS key slots per wavefront

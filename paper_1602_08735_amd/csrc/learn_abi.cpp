@@ -12,6 +12,7 @@
 
 namespace vsbpp {
 int32_t check_options_public(const vsbpp_options& o);
+int32_t check_heuristic_options_public(const vsbpp_options& o, int32_t heuristic);
 vsbpp_options resolve_options(const vsbpp_options* opt);
 }  // namespace vsbpp
 
@@ -82,6 +83,10 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     int32_t rc = vsbpp::check_options_public(o);
     if (rc != VSBPP_OK) return rc;
   }
+  {
+    const int32_t rc = vsbpp::check_heuristic_options_public(o, heuristic);
+    if (rc != VSBPP_OK) return rc;
+  }
   const bool ext = o.type_rule == VSBPP_TYPE_LEARNED ||
                    (dec && (dec->src || dec->force || dec->features || dec->info));
   if (ext && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
@@ -104,6 +109,7 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
   a.max_types = b->max_types;
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
+  a.active_limit = o.active_limit;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   if (dec) {

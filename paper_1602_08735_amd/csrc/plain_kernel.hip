@@ -279,7 +279,9 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 // SPILL: the wavefront's arrays (keys, position->id map, suffix minima) sit
 // in a device region of per_wave bytes per instance instead of LDS, for
 // instances whose bins do not fit a workgroup's LDS (plain runs only).
-template <int CRIT, typename K, bool EXT, bool SPILL>
+// BND: the bounded-active-bins code is compiled in (and taken when
+// a.active_limit > 0); unbounded plain runs use the instantiation without it.
+template <int CRIT, typename K, bool EXT, bool SPILL, bool BND>
 __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per_wave) {
   static_assert(!(EXT && SPILL), "decision hooks and the scorer run from LDS");
   using KT = KeyT<K>;
@@ -440,7 +442,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         wv = a.w[off + item];
       }
       int32_t sfx = 0x7FFFFFFF, next_min = 0x7FFFFFFF;
-      if constexpr (EXT) {
+      if (EXT || (BND && a.active_limit > 0)) {
         sfx = wave_suffix_min(q < m ? wv : 0x7FFFFFFF, lane);
         if (c + 1 < nch) next_min = uniform(smin[c + 1]);
       }
@@ -532,6 +534,38 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           }
         } else {
           // nothing fits: open a bin of the chosen type
+          if (BND && a.active_limit > 0) {
+            // Bounded runs: at most active_limit bins are open, and a bin
+            // that must open while that many are open first closes the
+            // fullest (least room, lowest index on ties).  A bin whose room
+            // is below every weight still to come can never take an item and
+            // is fuller than any other, so closing it at once changes no
+            // placement: the open bins that count are the live ones, and the
+            // key list is already in creation order.  The closed bin's key
+            // takes room 0, which no scan picks and compaction removes.
+            const int32_t tj = min(readlane(sfx, jj), next_min);
+            const int ngl = uniform((nlive + 255) >> 8);
+            K best = ~(K)0;
+            int open = 0;
+            for (int g = 0; g < ngl; ++g) {
+              K k[4];
+              load_group(keys, g, lane, k);
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const int pos = (g << 8) + (j << 6) + lane;
+                const K r = room_of<CRIT>(k[j]);
+                const bool live = pos < nlive && r >= (K)tj;
+                open += (int)__popcll(ballot(live));
+                best = min(best, live ? ((r << KT::SH) | (K)pos) : ~(K)0);
+              }
+            }
+            if (open >= a.active_limit) {
+              const int pf = (int)(wave_min(best) & KT::POS);
+              if (lane == (pf & 63))
+                keys[kidx(pf)] = CRIT == WF ? ((KT::R << KT::SH) | (K)pf) : (K)pf;
+              ++dead;
+            }
+          }
           const uint64_t fm = ballot(lane < n && cap_lane >= w);
           const int smallest = (int)__popcll(fm) - 1;
           int t = a.type_rule == 1 ? 0 : smallest;
@@ -634,12 +668,12 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
   }
 }
 
-template <int CRIT, typename K, bool EXT, bool SPILL>
+template <int CRIT, typename K, bool EXT, bool SPILL, bool BND>
 hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
   const size_t lds = SPILL ? 0
                            : per_wave * (size_t)wpb +
                                  (EXT ? plain_lds_block_extra(a.type_rule == 2) : 0);
-  auto kern = k_plain<CRIT, K, EXT, SPILL>;
+  auto kern = k_plain<CRIT, K, EXT, SPILL, BND>;
   static bool raised = false;
   if (lds > 65536 && !raised) {
     hipError_t e = allow_max_dynamic_lds(kern);
@@ -653,24 +687,30 @@ hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hi
 
 template <int CRIT, typename K>
 hipError_t launch_sel(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
-  if (a.spill) return launch_one<CRIT, K, false, true>(a, wpb, per_wave, grid, s);
-  return plain_ext(a) ? launch_one<CRIT, K, true, false>(a, wpb, per_wave, grid, s)
-                      : launch_one<CRIT, K, false, false>(a, wpb, per_wave, grid, s);
+  if (a.spill) return launch_one<CRIT, K, false, true, true>(a, wpb, per_wave, grid, s);
+  if (plain_ext(a)) return launch_one<CRIT, K, true, false, true>(a, wpb, per_wave, grid, s);
+  return a.active_limit > 0 ? launch_one<CRIT, K, false, false, true>(a, wpb, per_wave, grid, s)
+                            : launch_one<CRIT, K, false, false, false>(a, wpb, per_wave, grid, s);
 }
 
 template <int CRIT, typename K>
-int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill) {
+int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill, bool bounded) {
   int n = 0;
   hipError_t e;
   if (spill) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, true>, 64 * wpb,
-                                                     0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, true, true>,
+                                                     64 * wpb, 0);
   } else {
     const size_t lds = per_wave * (size_t)wpb + (ext ? plain_lds_block_extra(learned) : 0);
-    e = ext ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false>,
-                                                           64 * wpb, lds)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false>,
-                                                           64 * wpb, lds);
+    if (ext)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false, true>,
+                                                       64 * wpb, lds);
+    else if (bounded)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false, true>,
+                                                       64 * wpb, lds);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false, false>,
+                                                       64 * wpb, lds);
   }
   if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
@@ -706,14 +746,16 @@ hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
 
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave) {
   const bool ext = plain_ext(a), learned = a.type_rule == 2, spill = a.spill != nullptr;
+  const bool bnd = a.active_limit > 0;
+  const size_t lw = lds_per_wave;
   if (!wide) {
-    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lds_per_wave, ext, learned, spill);
-    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lds_per_wave, ext, learned, spill);
-    return occupancy<WF, uint32_t>(wpb, lds_per_wave, ext, learned, spill);
+    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lw, ext, learned, spill, bnd);
+    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lw, ext, learned, spill, bnd);
+    return occupancy<WF, uint32_t>(wpb, lw, ext, learned, spill, bnd);
   }
-  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lds_per_wave, ext, learned, spill);
-  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lds_per_wave, ext, learned, spill);
-  return occupancy<WF, uint64_t>(wpb, lds_per_wave, ext, learned, spill);
+  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lw, ext, learned, spill, bnd);
+  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lw, ext, learned, spill, bnd);
+  return occupancy<WF, uint64_t>(wpb, lw, ext, learned, spill, bnd);
 }
 
 }  // namespace vsbpp

@@ -20,6 +20,7 @@
 
 namespace vsbpp {
 int32_t check_options_public(const vsbpp_options& o);
+int32_t check_heuristic_options_public(const vsbpp_options& o, int32_t heuristic);
 vsbpp_options resolve_options(const vsbpp_options* opt);
 }  // namespace vsbpp
 
@@ -212,6 +213,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
     o.type_rule = VSBPP_TYPE_SMALLEST_FIT;  // shared checks below
   }
   int32_t rc = vsbpp::check_options_public(o);
+  if (rc == VSBPP_OK) rc = vsbpp::check_heuristic_options_public(o, heuristic);
   if (rc != VSBPP_OK) return rc;
   if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
@@ -235,6 +237,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   a.max_types = b->max_types;
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
+  a.active_limit = o.active_limit;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   a.model = learned ? d_model : nullptr;

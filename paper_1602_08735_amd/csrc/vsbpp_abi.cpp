@@ -20,6 +20,7 @@ using vsbpp::BatchArgs;
 
 namespace vsbpp {
 int32_t check_options_public(const vsbpp_options& o);
+int32_t check_heuristic_options_public(const vsbpp_options& o, int32_t heuristic);
 vsbpp_options resolve_options(const vsbpp_options* opt);
 }  // namespace vsbpp
 
@@ -53,6 +54,13 @@ int32_t check_options(const vsbpp_options& o) {
   if (o.type_rule != VSBPP_TYPE_SMALLEST_FIT && o.type_rule != VSBPP_TYPE_LARGEST)
     return VSBPP_E_OPTION;
   if (o.force_criterion < -1 || o.force_criterion > VSBPP_WF) return VSBPP_E_OPTION;
+  if (o.active_limit < 0) return VSBPP_E_OPTION;
+  return VSBPP_OK;
+}
+
+// options that only some heuristics take
+int32_t check_heuristic_options(const vsbpp_options& o, int32_t heuristic) {
+  if (o.active_limit > 0 && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
 
@@ -327,6 +335,7 @@ void vsbpp_options_init(vsbpp_options* opt) {
   opt->type_rule = VSBPP_TYPE_SMALLEST_FIT;
   opt->force_criterion = -1;
   opt->order = nullptr;
+  opt->active_limit = 0;
 }
 
 const char* vsbpp_strerror(int32_t code) {
@@ -359,6 +368,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   int32_t rc = check_instance(weights, m, capacities, n, heuristic, o, true);
   if (rc != VSBPP_OK) return rc;
   rc = check_options(o);
+  if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
   if (rc != VSBPP_OK) return rc;
 
   std::lock_guard<std::mutex> lk(g_mu);
@@ -402,6 +412,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   a.max_types = n;
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
+  a.active_limit = o.active_limit;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   DevBuf<unsigned char> dspill;
@@ -455,6 +466,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
     return VSBPP_E_SIZE;
   if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
   int32_t rc = check_options(o);
+  if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
   if (rc != VSBPP_OK) return rc;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -478,6 +490,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
   a.max_types = max_types;
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
+  a.active_limit = o.active_limit;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   return launch_batch(a, heuristic, (hipStream_t)hip_stream);
@@ -536,5 +549,8 @@ int32_t vsbpp_exact_batch(const vsbpp_batch* b, void* hip_stream) {
 
 namespace vsbpp {
 int32_t check_options_public(const vsbpp_options& o) { return check_options(o); }
+int32_t check_heuristic_options_public(const vsbpp_options& o, int32_t heuristic) {
+  return check_heuristic_options(o, heuristic);
+}
 vsbpp_options resolve_options(const vsbpp_options* opt) { return resolve(opt); }
 }  // namespace vsbpp

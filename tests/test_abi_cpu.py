@@ -63,6 +63,11 @@ def test_option_checks(V):
         with pytest.raises(V.VsbppError) as e:
             V.pack([1, 2, 3], [10, 5], "H1", **kw)
         assert e.value.code == -6, kw
+    # a bound on the open bins: not negative, plain heuristics only
+    for h, k in (("BF", -1), ("H1", 2), ("H2", 1)):
+        with pytest.raises(V.VsbppError) as e:
+            V.pack([1, 2, 3], [10, 5], h, active_limit=k)
+        assert e.value.code == -6, (h, k)
 
 
 def test_batch_host_checks(V):
@@ -87,6 +92,17 @@ def test_batch_host_checks(V):
     bad = V.options(s2=9)
     assert L.vsbpp_pack_batch(3, *args, 10, 3, 100, 0, ctypes.byref(bad), None, None, *outs,
                               None) == -6
+    for h, k in ((0, -1), (3, 4), (4, 1)):
+        bounded = V.options(active_limit=k)
+        assert L.vsbpp_pack_batch(3, *args, 10, 3, 100, h, ctypes.byref(bounded), None, None,
+                                  *outs, None) == -6, (h, k)
+    # a caller built against the shorter options struct (no active_limit)
+    short = V.options()
+    short.struct_size = V.Options.active_limit.offset
+    short.active_limit = -1  # beyond the declared size: not read
+    if not V.device_ok():
+        assert L.vsbpp_pack_batch(3, *args, 10, 3, 100, 0, ctypes.byref(short), None, None,
+                                  *outs, None) == -7
 
 
 def test_no_device_reports_device_error(V):
