@@ -242,6 +242,7 @@ static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_
       return ORC_E_OPTION;
     if (o->force_crit < -1 || o->force_crit > ORC_WF) return ORC_E_OPTION;
     if (o->active_limit < 0 || (o->active_limit > 0 && heuristic > ORC_WF)) return ORC_E_OPTION;
+    if (o->downsize != 0 && o->downsize != 1) return ORC_E_OPTION;
     if (o->order) {
       /* must be a permutation of [0,m) */
       char* seen = (char*)calloc((size_t)m, 1);
@@ -455,7 +456,7 @@ int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int3
   orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0};
+  orc_opts o = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, 0};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label = -1;
   if (rc >= 0 && d < count) {
@@ -467,7 +468,7 @@ int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int3
       if (!((feasible >> k1) & 1u)) continue;
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < n; ++k2) {
-        orc_opts f = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0};
+        orc_opts f = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, 0};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }
@@ -618,10 +619,42 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
   return base;
 }
 
+static int32_t orc_pack_run(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                            int32_t heuristic, const orc_opts* opt, int32_t* assign,
+                            int32_t* types, int64_t* cost, orc_stats* stats);
+
+/* Downsizing (with the LARGEST type rule, a pass the paper's Section 1 open
+ * type choice invites): a bin's cost is its capacity, so once the packing
+ * is fixed every bin can take the smallest type whose capacity holds its
+ * load.  Bins, ids and the item assignment are unchanged; types and the
+ * cost are recomputed. */
+static void downsize_bins(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                          const int32_t* assign, int32_t nb, int32_t* types, int64_t* cost) {
+  int64_t* load = (int64_t*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int64_t));
+  for (int32_t j = 0; j < m; ++j) load[assign[j]] += w[j];
+  *cost = 0;
+  for (int32_t b = 0; b < nb; ++b) {
+    int32_t t = 0;
+    for (int32_t k = 0; k < n; ++k)
+      if (caps[k] >= load[b]) t = k;
+    types[b] = t;
+    *cost += caps[t];
+  }
+  free(load);
+}
+
 int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                  int32_t heuristic, const orc_opts* opt, int32_t* assign,
                  int32_t* types, int64_t* cost, orc_stats* stats) {
-  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0};
+  const int32_t nb = orc_pack_run(w, m, caps, n, heuristic, opt, assign, types, cost, stats);
+  if (nb > 0 && opt && opt->downsize) downsize_bins(w, m, caps, n, assign, nb, types, cost);
+  return nb;
+}
+
+static int32_t orc_pack_run(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                            int32_t heuristic, const orc_opts* opt, int32_t* assign,
+                            int32_t* types, int64_t* cost, orc_stats* stats) {
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0};
   const orc_opts* o = opt ? opt : &def;
   if (!assign || !types || !cost) return ORC_E_NULL;
   int32_t rc = validate(w, m, caps, n, heuristic, o);

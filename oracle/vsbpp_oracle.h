@@ -72,6 +72,8 @@ typedef struct {
   int32_t* trace_count;   /* number of decisions of the run                */
   int32_t active_limit;   /* plain FF/BF/WF: at most this many bins open at
                              once (0: no limit); see run_plain               */
+  int32_t downsize;       /* 1: after packing, every bin takes the smallest
+                             type that holds its load (see downsize_bins)   */
 } orc_opts;
 
 typedef struct {

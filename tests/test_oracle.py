@@ -403,3 +403,55 @@ def test_bounded_option_checks(orc):
         with pytest.raises(orc.OracleError) as e:
             orc.pack([1, 2], [10], h, active_limit=3)
         assert e.value.code == -6
+
+
+# ---------------------------------------------------------------------------
+# Downsizing: after packing, every bin takes the smallest type holding its
+# load.
+# ---------------------------------------------------------------------------
+
+def test_downsize_hand_example(orc):
+    """B = {10, 7, 4}, LARGEST, BF, w = [3, 4, 8, 1]: 3 and 4 share b0 (load
+    7), 8 opens b1, 1 goes to b1 (room after 1 < 2).  Loads 7 and 9: b0 can
+    shrink to B_2 = 7, b1 stays B_1.  Cost 20 -> 17."""
+    plain = orc.pack([3, 4, 8, 1], [10, 7, 4], "BF", type_rule=orc.TYPE_LARGEST)
+    assert plain.assignment.tolist() == [0, 0, 1, 1] and plain.cost == 20
+    r = orc.pack([3, 4, 8, 1], [10, 7, 4], "BF", type_rule=orc.TYPE_LARGEST, downsize=True)
+    assert r.assignment.tolist() == [0, 0, 1, 1]
+    assert r.bin_types.tolist() == [1, 0] and r.cost == 17
+
+
+def test_downsize_keeps_smallest_fit_plain_runs(orc):
+    """A plain run's bin opens with the smallest type holding its first
+    item and its load stays within that type, so no smaller type holds the
+    load: downsizing changes nothing."""
+    rng = np.random.default_rng(81)
+    for _ in range(40):
+        b = inputs.random_batch(rng, 1, 1, 300)
+        w, caps, _ = b.instance(0)
+        for h in ("FF", "BF", "WF"):
+            u = orc.pack(w, caps, h)
+            d = orc.pack(w, caps, h, downsize=True)
+            assert d.bin_types.tolist() == u.bin_types.tolist() and d.cost == u.cost
+
+
+def test_downsize_every_heuristic(orc):
+    """Same bins and assignment; each bin's type is the smallest holding its
+    load; the cost never rises, and a single bin type changes nothing."""
+    rng = np.random.default_rng(82)
+    for _ in range(30):
+        b = inputs.random_batch(rng, 1, 1, 200)
+        w, caps, _ = b.instance(0)
+        for h in ("FF", "BF", "WF", "H1", "H2"):
+            for rule in (orc.TYPE_SMALLEST_FIT, orc.TYPE_LARGEST):
+                u = orc.pack(w, caps, h, seed=5, type_rule=rule)
+                d = orc.pack(w, caps, h, seed=5, type_rule=rule, downsize=True)
+                assert d.assignment.tolist() == u.assignment.tolist()
+                assert d.cost <= u.cost
+                loads = np.bincount(d.assignment, weights=w, minlength=d.nbins)
+                for bi in range(d.nbins):
+                    fit = [k for k in range(len(caps)) if caps[k] >= loads[bi]]
+                    assert d.bin_types[bi] == max(fit)
+                assert d.cost == sum(int(caps[t]) for t in d.bin_types)
+                if len(caps) == 1:
+                    assert d.cost == u.cost
