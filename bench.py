@@ -84,7 +84,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--heuristics", default=",".join(HEURISTICS + LEARNED))
     ap.add_argument("--active-limit", type=int, default=16,
-                    help="open-bin bound of the bounded FF/BF/WF leg (0 skips it)")
+                    help="open-bin bound of the bounded FF/BF/WF variants (0 skips them)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the method-variant leg (bounded bins, downsizing)")
     ap.add_argument("--exact-instances", type=int, default=16384,
                     help="instances of the exact-solver leg (0 skips it)")
     ap.add_argument("--no-graph", action="store_true")
@@ -244,21 +246,30 @@ def exact_leg(V, torch, n_inst, steps, warmup, cpu_sample):
     return out
 
 
-def bounded_leg(V, torch, db, lb, limit, steps, warmup):
-    """Plain FF/BF/WF with at most `limit` bins open (the fullest closes),
-    as autotuned graph plans on the step's batch: time and cost/LB."""
+def variants_leg(V, torch, db, lb, limit, steps, warmup):
+    """The method variants on the step's batch, each an autotuned graph plan:
+    plain FF/BF/WF with at most `limit` bins open (the fullest closes), and
+    the largest type rule with and without the downsizing pass, which gives
+    every bin the smallest type holding its load.  Time and cost/LB."""
     import numpy as np
 
+    runs = [(f"{c} K={limit}", c, dict(active_limit=limit)) for c in ("FF", "BF", "WF")]
+    runs += [("BF largest", "BF", dict(type_rule=V.TYPE_LARGEST)),
+             ("BF largest+downsize", "BF", dict(type_rule=V.TYPE_LARGEST, downsize=True)),
+             ("H1 +downsize", "H1", dict(downsize=True)),
+             ("H2 +downsize", "H2", dict(downsize=True))]
     stream = torch.cuda.current_stream()
     out = {}
-    for crit in ("FF", "BF", "WF"):
+    for label, h, kw in runs:
+        if label.endswith(f"K={limit}") and limit <= 0:
+            continue
         o = V.DeviceBatch.__new__(V.DeviceBatch)
         o.__dict__.update(db.__dict__)
         o.assignment = torch.empty_like(db.assignment)
         o.bin_types = torch.empty_like(db.bin_types)
         o.nbins = torch.empty_like(db.nbins)
         o.cost = torch.empty_like(db.cost)
-        p = V.Plan(o, crit, graph=True, autotune=True, active_limit=limit)
+        p = V.Plan(o, h, graph=True, autotune=True, **kw)
         for _ in range(warmup):
             p.run(stream)
         torch.cuda.synchronize()
@@ -270,11 +281,10 @@ def bounded_leg(V, torch, db, lb, limit, steps, warmup):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         if (o.nbins.cpu().numpy() < 1).any():
-            raise RuntimeError(f"bounded {crit}: device reported instance errors")
+            raise RuntimeError(f"{label}: device reported instance errors")
         cost = o.cost.cpu().numpy().astype(np.float64)
-        out[f"{crit} K={limit}"] = {"ms": ms, "items_per_s": db.total / (ms / 1e3),
-                                    "mean_cost_over_lb": float((cost / lb).mean()),
-                                    "launch": p.launch()}
+        out[label] = {"ms": ms, "items_per_s": db.total / (ms / 1e3),
+                      "mean_cost_over_lb": float((cost / lb).mean()), "launch": p.launch()}
         p.close()
     return out
 
@@ -489,9 +499,9 @@ def main():
         "learned_vs_plain": learned_cmp,
         "launch_shapes": {h: plans[h].launch() for h in heuristics},
     }
-    if args.active_limit > 0:
-        out["bounded_active_bins"] = bounded_leg(V, torch, db, lb, args.active_limit,
-                                                 args.steps, args.warmup)
+    if not args.no_variants:
+        out["variants"] = variants_leg(V, torch, db, lb, args.active_limit, args.steps,
+                                       args.warmup)
     if args.exact_instances > 0:
         out["exact_solver"] = exact_leg(V, torch, args.exact_instances, args.steps, args.warmup,
                                         0 if args.no_cpu_baseline else args.exact_instances)

@@ -106,6 +106,16 @@ typedef struct vsbpp_options {
                                (Appended last: callers built against the
                                shorter struct keep working through
                                struct_size.)                                   */
+  int32_t downsize;         /* 1: after packing, every bin takes the smallest
+                               type whose capacity holds its load, and the cost
+                               is recomputed (bins and the assignment are
+                               kept).  With VSBPP_TYPE_LARGEST this is the
+                               "largest type, then shrink" rule.  A pass over
+                               the outputs, so it does not change the choices
+                               the heuristic made (H2's permutation minimum
+                               included).  0 (default) or 1, else
+                               VSBPP_E_OPTION; not with decision-hook entries
+                               that name a source instance.                   */
 } vsbpp_options;
 
 void vsbpp_options_init(vsbpp_options* opt);

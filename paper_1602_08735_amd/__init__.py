@@ -58,6 +58,7 @@ class Options(ctypes.Structure):
         ("force_criterion", ctypes.c_int32),
         ("order", ctypes.POINTER(ctypes.c_int32)),
         ("active_limit", ctypes.c_int32),
+        ("downsize", ctypes.c_int32),
     ]
 
 
@@ -97,7 +98,7 @@ def lib():
 
 
 def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT,
-            force_crit: int = -1, active_limit: int = 0) -> Options:
+            force_crit: int = -1, active_limit: int = 0, downsize: bool = False) -> Options:
     o = Options()
     lib().vsbpp_options_init(ctypes.byref(o))
     o.seed = seed & (2**64 - 1)
@@ -106,6 +107,7 @@ def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMAL
     o.type_rule = type_rule
     o.force_criterion = force_crit
     o.active_limit = active_limit
+    o.downsize = int(downsize)
     return o
 
 
@@ -131,7 +133,7 @@ def _heur(h) -> int:
 
 def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
          type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, order=None,
-         active_limit: int = 0) -> Packing:
+         active_limit: int = 0, downsize: bool = False) -> Packing:
     """One instance through vsbpp_pack_ex (host arrays, synchronous)."""
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.int32))
     c = np.ascontiguousarray(np.asarray(caps, dtype=np.int32))
@@ -139,7 +141,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     a = np.zeros(max(m, 1), dtype=np.int32)
     t = np.zeros(max(m, 1), dtype=np.int32)
     cost = ctypes.c_int64(0)
-    o = options(seed, s1, s2, type_rule, force_crit, active_limit)
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize)
     ordv = None
     if order is not None:
         ordv = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
@@ -183,13 +185,14 @@ class DeviceBatch:
 
 def pack_batch(db: DeviceBatch, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
                type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, stream=None,
-               use_order: bool = True, use_seeds: bool = True, active_limit: int = 0) -> None:
+               use_order: bool = True, use_seeds: bool = True, active_limit: int = 0,
+               downsize: bool = False) -> None:
     """Launches vsbpp_pack_batch on the given torch stream (default: current).
     Results land in db.assignment / db.bin_types / db.nbins / db.cost."""
     import torch
 
     s = stream if stream is not None else torch.cuda.current_stream()
-    o = options(seed, s1, s2, type_rule, force_crit, active_limit)
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize)
     ptr = lambda x: None if x is None else x.data_ptr()
     rc = lib().vsbpp_pack_batch(
         db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
@@ -260,7 +263,7 @@ class Plan:
                  graph: bool = False, autotune: bool = False, seed: int = 0, s1: int = 10,
                  s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
                  use_order: bool = True, use_seeds: bool = True, model_ptr=None,
-                 active_limit: int = 0):
+                 active_limit: int = 0, downsize: bool = False):
         L = _plan_lib()
         ptr = lambda x: None if x is None else x.data_ptr()
         self.db = db
@@ -269,7 +272,7 @@ class Plan:
             ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
             db.max_items, db.max_types, db.max_cap,
             ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
-        o = options(seed, s1, s2, type_rule, force_crit, active_limit)
+        o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize)
         lp = None
         if launch is not None:
             lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
@@ -399,7 +402,7 @@ def _desc(db: DeviceBatch, use_order=True, use_seeds=True, outputs=True, num=Non
 def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force=None,
                   features=None, info=None, nbins=None, cost=None, seed: int = 0,
                   type_rule: int = TYPE_SMALLEST_FIT, stream=None,
-                  active_limit: int = 0) -> None:
+                  active_limit: int = 0, downsize: bool = False) -> None:
     """vsbpp_pack_batch_ex.  With `src` (int32 tensor [E]) the batch has E
     entries reading instance src[e]; nbins/cost then receive E results (pass
     tensors of size E)."""
@@ -414,7 +417,7 @@ def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force
     if cost is not None:
         d.cost = cost.data_ptr()
     dec = _Decisions(ptr(src), ptr(force), ptr(features), ptr(info))
-    o = options(seed, type_rule=type_rule, active_limit=active_limit)
+    o = options(seed, type_rule=type_rule, active_limit=active_limit, downsize=downsize)
     rc = L.vsbpp_pack_batch_ex(ctypes.byref(d), _heur(heuristic), ctypes.byref(o), model_ptr,
                                ctypes.byref(dec), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:

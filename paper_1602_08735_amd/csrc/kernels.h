@@ -33,6 +33,7 @@ struct BatchArgs {
   int32_t type_rule;        // 0 smallest fit, 1 largest
   int32_t force_crit;       // -1 or 0/1/2 (H1/H2 only)
   int32_t active_limit;     // plain FF/BF/WF: bins open at once (0: no limit)
+  int32_t downsize;         // 1: a pass after packing gives every bin its smallest type
   int32_t s1;               // H1 items per sublist
   int32_t s2;               // H2 subset size
   int32_t slots;            // plain kernel: LDS key slots per wavefront
@@ -93,6 +94,9 @@ hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStr
 hipError_t launch_bounds(int32_t num, const int32_t* w, const int64_t* item_off,
                          const int32_t* caps, const int32_t* cap_off, int64_t* out,
                          hipStream_t s);
+
+// downsizing pass over a packed batch (bin types and costs rewritten)
+hipError_t launch_downsize(const BatchArgs& a, hipStream_t s);
 
 // exact optimum of instances with at most 12 items (subset dynamic
 // programme, one workgroup of `block` threads (128..512, a multiple of 64)

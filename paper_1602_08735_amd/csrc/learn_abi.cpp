@@ -87,6 +87,9 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     const int32_t rc = vsbpp::check_heuristic_options_public(o, heuristic);
     if (rc != VSBPP_OK) return rc;
   }
+  // downsizing rewrites the bin types, which entries with a source instance
+  // do not write
+  if (o.downsize && has_src) return VSBPP_E_OPTION;
   const bool ext = o.type_rule == VSBPP_TYPE_LEARNED ||
                    (dec && (dec->src || dec->force || dec->features || dec->info));
   if (ext && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
@@ -110,6 +113,7 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
+  a.downsize = o.downsize;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   if (dec) {

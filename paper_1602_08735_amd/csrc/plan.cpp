@@ -238,6 +238,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
+  a.downsize = o.downsize;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   a.model = learned ? d_model : nullptr;

@@ -55,6 +55,7 @@ int32_t check_options(const vsbpp_options& o) {
     return VSBPP_E_OPTION;
   if (o.force_criterion < -1 || o.force_criterion > VSBPP_WF) return VSBPP_E_OPTION;
   if (o.active_limit < 0) return VSBPP_E_OPTION;
+  if (o.downsize != 0 && o.downsize != 1) return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
 
@@ -292,6 +293,14 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     e = heuristic == VSBPP_H1 ? launch_h1_grid(a, wide, nbs, block, grid, s)
                               : launch_h2_grid(a, h2_kernel(a, block), nbs, block, grid, s);
   }
+  if (e == hipSuccess && a.downsize) {
+    e = launch_downsize(a, s);
+    if (e != hipSuccess) {
+      set_last_error("downsize launch", e);
+      (void)hipGetLastError();
+      return VSBPP_E_DEVICE;
+    }
+  }
   if (e == hipSuccess) return VSBPP_OK;
 fail:
   set_last_error(heuristic <= VSBPP_WF ? "plain launch" : heuristic == VSBPP_H1 ? "H1 launch"
@@ -336,6 +345,7 @@ void vsbpp_options_init(vsbpp_options* opt) {
   opt->force_criterion = -1;
   opt->order = nullptr;
   opt->active_limit = 0;
+  opt->downsize = 0;
 }
 
 const char* vsbpp_strerror(int32_t code) {
@@ -413,6 +423,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
+  a.downsize = o.downsize;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   DevBuf<unsigned char> dspill;
@@ -491,6 +502,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
   a.type_rule = o.type_rule;
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
+  a.downsize = o.downsize;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   return launch_batch(a, heuristic, (hipStream_t)hip_stream);

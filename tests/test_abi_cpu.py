@@ -68,6 +68,11 @@ def test_option_checks(V):
         with pytest.raises(V.VsbppError) as e:
             V.pack([1, 2, 3], [10, 5], h, active_limit=k)
         assert e.value.code == -6, (h, k)
+    # downsizing is 0 or 1
+    for d in (-1, 2):
+        with pytest.raises(V.VsbppError) as e:
+            V.pack([1, 2, 3], [10, 5], "H2", downsize=d)
+        assert e.value.code == -6, d
 
 
 def test_batch_host_checks(V):
