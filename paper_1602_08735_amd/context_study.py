@@ -1,0 +1,96 @@
+"""Context study: the heuristics on the shapes of the paper's Section 7
+workloads, best cost over seeded runs, next to the paper's own figures.
+
+* Group 2 (Table 7): the five printed multisets of m = 1000 items, bin types
+  {10, 20, 30, 40}.  Table 7 gives the second heuristic's best cost.
+* Group 3 (Table 3): m items with weights uniform in {1..20}, bin types
+  {100, 200, 300}.  The paper generated its lists of m >= 5000 this way and
+  took its m <= 1000 lists from a benchmark set that is not available here;
+  the same generator stands in for those.  Table 3 gives both heuristics'
+  best costs.
+
+The paper's item orders and random draws are unknown, so the figures can
+only be compared as context, not reproduced.  Each instance runs as `runs`
+batch entries.
+* H1/H2 draw Rule 1's permutation and Rule 3's criteria from each entry's own
+  generator key.
+* Plain Best Fit packs each entry's seeded random order.
+
+Run on a GPU: ``python -m paper_1602_08735_amd.context_study [--runs 64]``
+(prints a Markdown table).
+"""
+from __future__ import annotations
+
+import argparse
+
+# Table 7: total item weight and the second heuristic's best reached solution
+PAPER_TABLE7 = {"a": (10250, 11490), "b": (11600, 12990), "c": (11000, 12260),
+                "d": (9400, 10460), "e": (7000, 8310)}
+# Table 3: total item weight, first and second heuristic's best reached solution
+PAPER_TABLE3 = {100: (1119, 1600, 2300), 200: (2171, 3800, 4300), 500: (5511, 9900, 10600),
+                1000: (10459, 21400, 21200), 5000: (53252, 117100, 112600),
+                10000: (105516, 226600, 200800), 50000: (526327, 1153900, 1009200),
+                100000: (1051854, 2308800, 2016200)}
+
+# (label, heuristic, use the entry's order, plan options)
+RUNS = (("H1", "H1", False, {}),
+        ("H2", "H2", False, {}),
+        ("H2 +ds", "H2", False, {"downsize": True}),
+        ("BF", "BF", True, {}),
+        ("BF largest +ds", "BF", True, {"type_rule": 1, "downsize": True}))
+
+
+def best_costs(V, torch, batch):
+    """{label: (best cost, mean cost)} over the batch's entries, and the
+    lower bound max(LB_cap, LB_big) of the (shared) instance."""
+    import numpy as np
+
+    db = V.DeviceBatch(batch)
+    lbt = torch.empty(3 * db.n, dtype=torch.int64, device="cuda")
+    V.lower_bounds(db, lbt)
+    out = {}
+    for label, h, use_order, kw in RUNS:
+        p = V.Plan(db, h, use_order=use_order, **kw)
+        p.run()
+        torch.cuda.synchronize()
+        nb = db.nbins.cpu().numpy()
+        if (nb < 1).any():
+            raise RuntimeError(f"{label}: device reported instance errors")
+        c = db.cost.cpu().numpy()
+        out[label] = (int(c.min()), float(c.mean()))
+        p.close()
+    l3 = lbt.cpu().numpy().reshape(-1, 3)
+    return out, int(max(l3[0, 1], l3[0, 2])), int(l3[0, 0])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--runs", type=int, default=64)
+    args = ap.parse_args(argv)
+    import torch
+
+    import paper_1602_08735_amd as V
+    from paper_1602_08735_amd import inputs
+
+    labels = [r[0] for r in RUNS]
+    print(f"Group 2 (best of {args.runs} seeded runs; U = total weight / cost)\n")
+    print("| instance | total | LB | paper H2 (U) | " + " | ".join(labels) + " |")
+    print("|---|---|---|---|" + "---|" * len(labels))
+    for name, (tw, paper) in PAPER_TABLE7.items():
+        res, lb, total = best_costs(V, torch, inputs.group2_runs(name, args.runs))
+        assert total == tw
+        cells = [f"{res[k][0]} ({total / res[k][0]:.3f})" for k in labels]
+        print(f"| {name} | {total} | {lb} | {paper} ({tw / paper:.3f}) | " + " | ".join(cells)
+              + " |")
+    print(f"\nGroup 3 shapes (best of {args.runs} seeded runs; paper: its own lists)\n")
+    print("| m | total (paper's) | LB | paper H1 / H2 (U) | " + " | ".join(labels) + " |")
+    print("|---|---|---|---|" + "---|" * len(labels))
+    for m, (tw, p1, p2) in PAPER_TABLE3.items():
+        res, lb, total = best_costs(V, torch, inputs.group3_like(m, args.runs))
+        cells = [f"{res[k][0]} ({total / res[k][0]:.3f})" for k in labels]
+        print(f"| {m} | {total} ({tw}) | {lb} | {p1} / {p2} ({tw / p1:.3f} / {tw / p2:.3f}) | "
+              + " | ".join(cells) + " |")
+
+
+if __name__ == "__main__":
+    main()

@@ -226,6 +226,46 @@ def small_uniform(n_instances: int = 16384, m: int = 12, seed: int = 12) -> Batc
     return make_batch(ws, cs, None, seeds, {"workload": "small-uniform", "m": m})
 
 
+# Section 7, Group 2: five instances of m = 1000 items given as
+# weight(count) multisets, bin types {10, 20, 30, 40}.
+GROUP2_CAPS = (40, 30, 20, 10)
+GROUP2_MULTISETS = {
+    "a": ((2, 250), (5, 150), (11, 150), (14, 150), (15, 150), (20, 150)),
+    "b": ((7, 200), (10, 200), (12, 200), (14, 200), (15, 200)),
+    "c": ((2, 100), (4, 100), (5, 100), (8, 100), (9, 100), (13, 100), (15, 100), (16, 100),
+          (18, 100), (20, 100)),
+    "d": ((1, 150), (3, 50), (4, 100), (5, 50), (7, 100), (9, 50), (10, 50), (11, 50),
+          (12, 50), (13, 100), (15, 50), (16, 50), (18, 100), (20, 50)),
+    "e": ((3, 500), (11, 500)),
+}
+
+
+def group2_runs(name: str, runs: int, seed: int = 7) -> Batch:
+    """`runs` entries of one Group 2 instance (Section 7), each with its own
+    seeded item order and generator key; the multiset's items are listed in
+    the printed order, so the orders stand in for the unknown one."""
+    w = np.concatenate([np.full(c, v, dtype=np.int32) for v, c in GROUP2_MULTISETS[name]])
+    rng = np.random.default_rng([seed, ord(name)])
+    orders = [rng.permutation(w.size).astype(np.int32) for _ in range(runs)]
+    caps = np.array(GROUP2_CAPS, dtype=np.int32)
+    return make_batch([w] * runs, [caps] * runs, orders,
+                      rng.integers(0, 2**63, size=runs).astype(np.uint64),
+                      {"workload": f"group2-{name}"})
+
+
+def group3_like(m: int, runs: int, seed: int = 3) -> Batch:
+    """`runs` entries of one instance shaped like Section 7's Group 3: m
+    weights uniform in {1..20} (the paper's generated lists), bin types
+    {100, 200, 300}; seeded item orders and generator keys per entry."""
+    rng = np.random.default_rng([seed, m])
+    w = rng.integers(1, 21, size=m).astype(np.int32)
+    orders = [rng.permutation(m).astype(np.int32) for _ in range(runs)]
+    caps = np.array([300, 200, 100], dtype=np.int32)
+    return make_batch([w] * runs, [caps] * runs, orders,
+                      rng.integers(0, 2**63, size=runs).astype(np.uint64),
+                      {"workload": f"group3-like-{m}"})
+
+
 def random_batch(rng: np.random.Generator, n_instances: int, m_lo: int, m_hi: int,
                  n_lo: int = 1, n_hi: int = 7, b1_hi: int = 1000) -> Batch:
     """Random mixed batch for parity tests (ragged sizes, any n, any B_1)."""

@@ -455,3 +455,23 @@ def test_downsize_every_heuristic(orc):
                 assert d.cost == sum(int(caps[t]) for t in d.bin_types)
                 if len(caps) == 1:
                     assert d.cost == u.cost
+
+
+def test_group2_builders_match_the_printed_multisets():
+    """The context study's Group 2 instances are the multisets of Section 7
+    (fixture) and reproduce Table 7's total weights; every entry holds the
+    same items in its own order."""
+    g = golden("group2_multisets.json")
+    for name, ms in g["instances"].items():
+        assert [tuple(x) for x in ms] == list(inputs.GROUP2_MULTISETS[name])
+        b = inputs.group2_runs(name, 3)
+        ref = None
+        for i in range(3):
+            w, caps, order = b.instance(i)
+            assert w.size == 1000 and int(w.sum()) == g["table7_total_weight"][name]
+            assert caps.tolist() == g["caps"] and sorted(order.tolist()) == list(range(1000))
+            ref = w if ref is None else ref
+            assert np.array_equal(w, ref)
+    b = inputs.group3_like(500, 2)
+    w, caps, _ = b.instance(0)
+    assert caps.tolist() == [300, 200, 100] and w.min() >= 1 and w.max() <= 20
