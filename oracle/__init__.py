@@ -133,6 +133,10 @@ def lib():
         L.orc_rollout_label.restype = ctypes.c_int32
         L.orc_rollout_label.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, i64p]
+        L.orc_rollout_label_ex.restype = ctypes.c_int32
+        L.orc_rollout_label_ex.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, i64p]
         L.orc_lb_sum.restype = ctypes.c_int64
         L.orc_lb_sum.argtypes = [i32p, ctypes.c_int32]
         _lib = L
@@ -307,10 +311,14 @@ def mlp_forward(model: Model, x) -> np.ndarray:
     return z[:model.n_out].copy()
 
 
-def rollout_label(weights, caps, crit: int, d: int):
-    """(label, values) of decision d of a plain run (depth-2 lookahead)."""
+def rollout_label(weights, caps, crit: int, d: int, *, type_rule: int = TYPE_SMALLEST_FIT,
+                  downsize: bool = False):
+    """(label, values) of decision d of a plain run (depth-2 lookahead) whose
+    base rule opens bins by `type_rule`, costs after the downsizing pass when
+    `downsize`."""
     w, c = _i32(weights), _i32(caps)
     vals = np.zeros(c.size, dtype=np.int64)
-    lab = lib().orc_rollout_label(_p32(w), int(w.size), _p32(c), int(c.size), crit, d,
-                                  vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    lab = lib().orc_rollout_label_ex(_p32(w), int(w.size), _p32(c), int(c.size), crit, d,
+                                     int(type_rule), int(downsize),
+                                     vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return int(lab), vals

@@ -449,14 +449,21 @@ static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32
 
 int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                           int32_t crit, int32_t d, int64_t* values) {
+  return orc_rollout_label_ex(w, m, caps, n, crit, d, ORC_TYPE_SMALLEST_FIT, 0, values);
+}
+
+int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                             int32_t crit, int32_t d, int32_t type_rule, int32_t downsize,
+                             int64_t* values) {
   if (!w || !caps || !values) return ORC_E_NULL;
   if (crit < ORC_FF || crit > ORC_WF || d < 0) return ORC_E_OPTION;
+  if (type_rule != ORC_TYPE_SMALLEST_FIT && type_rule != ORC_TYPE_LARGEST) return ORC_E_OPTION;
   int32_t* assign = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
   int32_t* types = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
   orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, 0};
+  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label = -1;
   if (rc >= 0 && d < count) {
@@ -468,7 +475,7 @@ int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int3
       if (!((feasible >> k1) & 1u)) continue;
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < n; ++k2) {
-        orc_opts f = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, 0};
+        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }

@@ -124,6 +124,12 @@ void orc_mlp_forward(const orc_model* mdl, const float* x, float* z);
  * negative code. */
 int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                           int32_t crit, int32_t d, int64_t* values);
+/* The same with the base rule's type rule (ORC_TYPE_SMALLEST_FIT or
+ * ORC_TYPE_LARGEST) and every run's cost taken after the downsizing pass
+ * when downsize is 1. */
+int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                             int32_t crit, int32_t d, int32_t type_rule, int32_t downsize,
+                             int64_t* values);
 
 /* lower bounds on the optimum */
 int64_t orc_lb_sum(const int32_t* w, int32_t m);

@@ -87,9 +87,6 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     const int32_t rc = vsbpp::check_heuristic_options_public(o, heuristic);
     if (rc != VSBPP_OK) return rc;
   }
-  // downsizing rewrites the bin types, which entries with a source instance
-  // do not write
-  if (o.downsize && has_src) return VSBPP_E_OPTION;
   const bool ext = o.type_rule == VSBPP_TYPE_LEARNED ||
                    (dec && (dec->src || dec->force || dec->features || dec->info));
   if (ext && heuristic > VSBPP_WF) return VSBPP_E_OPTION;

@@ -300,13 +300,16 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
   int32_t* smin;
   int32_t* hist;
   float* hbuf;
+  int32_t* bload;  // downsized cost of source-instance entries: load of every bin id
   auto carve = [&](unsigned char* base) {
     keys = reinterpret_cast<K*>(base);
     pid = reinterpret_cast<Pid*>(base + (size_t)a.slots * sizeof(K));
     smin = reinterpret_cast<int32_t*>(base + (size_t)a.slots * sizeof(K) + pid_bytes);
     hist = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(smin) + smin_bytes);
     hbuf = reinterpret_cast<float*>(hist + 16);
+    bload = reinterpret_cast<int32_t*>(hbuf + 128);
   };
+  const bool dsl = EXT && plain_ds_loads(a);
   if constexpr (!SPILL) carve(smem + model_bytes + (size_t)wave * (size_t)per_wave);
   if constexpr (EXT) {
     if (a.type_rule == 2) {
@@ -523,6 +526,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         if (p >= 0) {
           // Rule 4: place into the chosen open bin
           if (lane == (p & 63)) keys[kidx(p)] = nk;
+          if (dsl && lane == 0) bload[pid[p]] += w;
           const K rnew = room_of<CRIT>(nk);
           if (rnew < (K)T) ++dead;
           if constexpr (EXT) {
@@ -645,6 +649,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)p) : ((room << KT::SH) | (K)p);
           if (lane == (p & 63)) keys[kidx(p)] = key;
           if (lane == 0) pid[p] = (Pid)id;
+          if (dsl && lane == 0) bload[id] = w;
           const bool out_types = !EXT || !a.src;
           typebuf = lane == (id & 63) ? t : typebuf;
           if (out_types && (id & 63) == 63) a.types[off + (id - 63) + lane] = typebuf;
@@ -661,6 +666,20 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     }
     if ((!EXT || !a.src) && (nb & 63) && lane < (nb & 63))
       a.types[off + (nb & ~63) + lane] = typebuf;
+    if (dsl) {
+      // downsized cost: every bin at the smallest capacity holding its load
+      int64_t ds = 0;
+      for (int id = lane; id < nb; id += kWave) {
+        const int32_t l = bload[id];
+        int32_t c = B1;
+        for (int k = 1; k < n; ++k) {
+          const int32_t ck = readlane(cap_lane, k);
+          c = ck >= l ? ck : c;
+        }
+        ds += c;
+      }
+      cost = wave_sum64(ds);
+    }
     if (lane == 0) {
       a.nbins[inst] = nb;
       a.cost[inst] = cost;
@@ -718,13 +737,14 @@ int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill, bool
 
 }  // namespace
 
-size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext) {
+size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext, bool ds_loads) {
   const size_t ks = wide ? 8 : 4, ps = wide ? 4 : 2;
   const size_t nch = ((size_t)max_items + 63) / 64;
   size_t b = (size_t)slots * ks;
   b += ((size_t)slots * ps + 15) & ~(size_t)15;
   b += (nch * 4 + 15) & ~(size_t)15;
   if (ext) b += 16 * 4 + 128 * 4;  // room histogram + hidden-layer scratch
+  if (ext && ds_loads) b += ((size_t)max_items * 4 + 15) & ~(size_t)15;  // bin loads
   return b;
 }
 

@@ -131,7 +131,7 @@ int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
   sh->slots = round_up(a.max_items, 256);
   if (!wide && sh->slots > 65536) return VSBPP_E_SIZE;
   const bool ext = plain_ext(a);
-  sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide, ext);
+  sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide, ext, plain_ds_loads(a));
   const size_t extra = ext ? plain_lds_block_extra(a.type_rule == 2) : 0;
   sh->spill = (size_t)device_info().max_lds_block < extra + sh->per_wave;
   if (sh->spill) {
@@ -293,7 +293,8 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     e = heuristic == VSBPP_H1 ? launch_h1_grid(a, wide, nbs, block, grid, s)
                               : launch_h2_grid(a, h2_kernel(a, block), nbs, block, grid, s);
   }
-  if (e == hipSuccess && a.downsize) {
+  // (entries with a source instance sum their downsized cost in the kernel)
+  if (e == hipSuccess && a.downsize && !a.src) {
     e = launch_downsize(a, s);
     if (e != hipSuccess) {
       set_last_error("downsize launch", e);

@@ -145,15 +145,18 @@ def test_forced_decisions(orc):
     assert np.array_equal(r.assignment, plain.assignment)
 
 
-def test_rollout_label_invariants(orc):
+@pytest.mark.parametrize("rule,ds", [(0, False), (1, True)])
+def test_rollout_label_invariants(orc, rule, ds):
+    """Base rule smallest fit, or largest type with costs after downsizing."""
     rng = np.random.default_rng(5)
     for crit in (0, 1, 2):
         for _ in range(4):
             w, caps = inputs.c2_instance(rng, 120)
-            plain = orc.pack(w, caps, crit, trace=True)
+            plain = orc.pack(w, caps, crit, trace=True, type_rule=rule, downsize=ds)
             dec = plain.stats["decisions"]
             for d in rng.choice(len(dec) - 1, size=4, replace=False):
-                lab, vals = orc.rollout_label(w, caps, crit, int(d))
+                lab, vals = orc.rollout_label(w, caps, crit, int(d), type_rule=rule,
+                                              downsize=ds)
                 feas = dec[d].feasible
                 assert (feas >> lab) & 1
                 for k in range(caps.size):
@@ -168,18 +171,19 @@ def test_rollout_label_invariants(orc):
                     assert lab == int(np.flatnonzero(vals == best)[0])
 
 
-def test_rollout_values_against_brute_force(orc):
+@pytest.mark.parametrize("rule,ds", [(0, False), (1, True)])
+def test_rollout_values_against_brute_force(orc, rule, ds):
     """Every rollout value is the cost of a valid packing: at least OPT."""
     rng = np.random.default_rng(6)
     for _ in range(60):
         w, caps = inputs.random_small(rng, m_max=9, n_max=4, b1_max=25)
-        plain = orc.pack(w, caps, "FF", trace=True)
+        plain = orc.pack(w, caps, "FF", trace=True, type_rule=rule, downsize=ds)
         nd = len(plain.stats["decisions"])
         if nd < 1:
             continue
         opt = orc.opt_subset_dp(w, caps)
         for d in range(nd):
-            lab, vals = orc.rollout_label(w, caps, 0, d)
+            lab, vals = orc.rollout_label(w, caps, 0, d, type_rule=rule, downsize=ds)
             assert lab >= 0
             assert vals[vals >= 0].min() >= opt
 
