@@ -71,19 +71,20 @@ def sample_decisions(ndec: np.ndarray, per_instance: int, rng: np.random.Generat
     return np.concatenate(src), np.concatenate(dd)
 
 
-def plain_decisions(db: DeviceBatch, crit) -> np.ndarray:
-    """Number of decisions of every instance's plain run (= its bins: every
-    bin of a plain run is opened at a decision)."""
+def plain_decisions(db: DeviceBatch, crit, type_rule: int = 0) -> np.ndarray:
+    """Number of decisions of every instance's plain run under the base type
+    rule (= its bins: every bin of a plain run is opened at a decision)."""
     import torch
 
-    pack_batch(db, crit)
+    pack_batch(db, crit, type_rule=type_rule)
     torch.cuda.synchronize()
     return db.nbins.cpu().numpy().copy()
 
 
-def decision_features(db: DeviceBatch, crit, src, d):
+def decision_features(db: DeviceBatch, crit, src, d, type_rule: int = 0):
     """Features [E,16] and (feasible mask, smallest fitting type) [E,2] of
-    decision d[e] of instance src[e]'s plain run (device tensors)."""
+    decision d[e] of instance src[e]'s plain run under the base type rule
+    (device tensors)."""
     import torch
 
     e = len(src)
@@ -95,17 +96,23 @@ def decision_features(db: DeviceBatch, crit, src, d):
     nb = torch.empty(e, dtype=torch.int32, device="cuda")
     cost = torch.empty(e, dtype=torch.int64, device="cuda")
     pack_batch_ex(db, crit, src=t_src, force=t_force, features=feats, info=info, nbins=nb,
-                  cost=cost)
+                  cost=cost, type_rule=type_rule)
     return feats, info
 
 
 def lookahead_labels(db: DeviceBatch, crit, src, d, info, n_types: int,
-                     chunk: int = 1 << 21, values: bool = False):
+                     chunk: int = 1 << 21, values: bool = False, type_rule: int = 0,
+                     downsize: bool = False):
     """Depth-2 lookahead labels of the given decisions: one rollout entry per
-    (decision, k1, k2), costs from the plain kernel with forced types, labels
-    from the reduction kernel."""
+    (decision, k1, k2), costs from the plain kernel with forced types (the
+    base type rule elsewhere, costs after downsizing when `downsize`), labels
+    from the reduction kernel (ties to the base rule's own choice: the
+    smallest fitting type, or type 0 under the largest-type rule)."""
     import torch
 
+    if type_rule == 1:
+        info = info.clone()
+        info[:, 1] = 0
     src = np.asarray(src, np.int32)
     d = np.asarray(d, np.int32)
     nd = len(src)
@@ -124,7 +131,8 @@ def lookahead_labels(db: DeviceBatch, crit, src, d, info, n_types: int,
         t_force = torch.as_tensor(np.ascontiguousarray(force.astype(np.int32)), device="cuda")
         nb = torch.empty(m * nn, dtype=torch.int32, device="cuda")
         cost = torch.empty(m * nn, dtype=torch.int64, device="cuda")
-        pack_batch_ex(db, crit, src=t_src, force=t_force, nbins=nb, cost=cost)
+        pack_batch_ex(db, crit, src=t_src, force=t_force, nbins=nb, cost=cost,
+                      type_rule=type_rule, downsize=downsize)
         rollout_labels(cost, info[a:b].contiguous(), m, n_types, labels[a:b],
                        None if vals is None else vals[a * n_types:b * n_types])
     return (labels, vals) if values else labels
@@ -153,9 +161,10 @@ def train(x, mask, label, n_out: int, *, epochs: int = 4, batch: int = 4096,
     return tr, losses
 
 
-def evaluate(db: DeviceBatch, crit, model_ptr, repeats: int = 3) -> dict:
-    """Plain (smallest fitting type) vs learned costs on a batch, their
-    cost/LB, and instances/s of both."""
+def evaluate(db: DeviceBatch, crit, model_ptr, repeats: int = 3, type_rule: int = 0,
+             downsize: bool = False) -> dict:
+    """Plain (the base type rule) vs learned costs on a batch, both with the
+    downsizing pass when `downsize`, their cost/LB, and instances/s of both."""
     import torch
 
     lb = torch.empty(3 * db.n, dtype=torch.int64, device="cuda")
@@ -163,8 +172,10 @@ def evaluate(db: DeviceBatch, crit, model_ptr, repeats: int = 3) -> dict:
     res = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for name in ("plain", "learned"):
-        run = (lambda: pack_batch(db, crit)) if name == "plain" else (
-            lambda: pack_batch_ex(db, crit, model_ptr=model_ptr, type_rule=TYPE_LEARNED))
+        run = (lambda: pack_batch(db, crit, type_rule=type_rule, downsize=downsize)) \
+            if name == "plain" else (
+            lambda: pack_batch_ex(db, crit, model_ptr=model_ptr, type_rule=TYPE_LEARNED,
+                                  downsize=downsize))
         run()
         torch.cuda.synchronize()
         ev[0].record()

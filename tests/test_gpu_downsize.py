@@ -91,13 +91,22 @@ def test_with_the_scorer(V, orc):
     exp = oracle_batch(b, "BF", type_rule=orc.TYPE_LEARNED,
                        model=orc.Model.from_buffer_copy(raw), downsize=True)
     assert_batch_equal(b, db, exp)
-    # entries that only report a cost of a source instance cannot be downsized
-    src = torch.zeros(4, dtype=torch.int32, device="cuda")
-    with pytest.raises(V.VsbppError) as e:
-        V.pack_batch_ex(db, "BF", src=src, nbins=torch.empty(4, dtype=torch.int32,
-                                                             device="cuda"),
-                        cost=torch.empty(4, dtype=torch.int64, device="cuda"), downsize=True)
-    assert e.value.code == -6
+
+    # entries that name a source instance write no bin types: the kernel sums
+    # their downsized cost itself (largest type, so the pass matters)
+    src_np = rng.integers(0, 64, size=200).astype(np.int32)
+    src = torch.as_tensor(src_np, device="cuda")
+    nb = torch.empty(200, dtype=torch.int32, device="cuda")
+    cost = torch.empty(200, dtype=torch.int64, device="cuda")
+    for h in ("FF", "BF", "WF"):
+        V.pack_batch_ex(db, h, src=src, nbins=nb, cost=cost, type_rule=V.TYPE_LARGEST,
+                        downsize=True)
+        torch.cuda.synchronize()
+        got_nb, got = nb.cpu().numpy(), cost.cpu().numpy()
+        for e, i in enumerate(src_np):
+            w, caps, _ = b.instance(int(i))
+            r = orc.pack(w, caps, h, type_rule=orc.TYPE_LARGEST, downsize=True)
+            assert got_nb[e] == r.nbins and got[e] == r.cost, (h, e)
 
 
 def test_error_instances_untouched(V, orc):

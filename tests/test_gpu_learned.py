@@ -78,35 +78,42 @@ def test_fused_inference_bit_exact(V, L, orc, h):
             assert np.array_equal(t[lo:lo + r.nbins], r.bin_types), (trial, i)
 
 
-def test_decision_features_bit_exact(V, L, orc):
+@pytest.mark.parametrize("rule", [0, 1])
+def test_decision_features_bit_exact(V, L, orc, rule):
+    """Decisions of the smallest-fit and of the largest-type base runs."""
     b = c2_batch(20, 400, 13)
     db = V.DeviceBatch(b)
     rng = np.random.default_rng(14)
     for crit in (0, 1, 2):
-        nd = L.plain_decisions(db, crit)
+        nd = L.plain_decisions(db, crit, type_rule=rule)
         src, d = L.sample_decisions(nd, 15, rng)
-        x, info = L.decision_features(db, crit, src, d)
+        x, info = L.decision_features(db, crit, src, d, type_rule=rule)
         x, info = x.cpu().numpy(), info.cpu().numpy()
         for e in range(len(src)):
             w, caps, _ = b.instance(int(src[e]))
-            dec = orc.pack(w, caps, crit, trace=True).stats["decisions"][int(d[e])]
+            dec = orc.pack(w, caps, crit, trace=True, type_rule=rule).stats["decisions"][int(d[e])]
             assert np.array_equal(x[e], np.array(dec.feat, np.float32)), (crit, e)
-            assert info[e, 0] == dec.feasible and info[e, 1] == dec.plain_type
+            smallest = max(k for k in range(caps.size) if caps[k] >= dec.weight)
+            assert info[e, 0] == dec.feasible and info[e, 1] == smallest
 
 
-def test_rollouts_and_labels_bit_exact(V, L, orc):
+@pytest.mark.parametrize("rule,ds", [(0, False), (1, True)])
+def test_rollouts_and_labels_bit_exact(V, L, orc, rule, ds):
+    """Base rule smallest fit, or largest type with every rollout's cost
+    after downsizing (summed in the packing kernel for these entries)."""
     b = c2_batch(16, 150, 15)
     db = V.DeviceBatch(b)
     rng = np.random.default_rng(16)
     for crit in (0, 1, 2):
-        nd = L.plain_decisions(db, crit)
+        nd = L.plain_decisions(db, crit, type_rule=rule)
         src, d = L.sample_decisions(nd, 6, rng)
-        _, info = L.decision_features(db, crit, src, d)
-        labels, vals = L.lookahead_labels(db, crit, src, d, info, 5, values=True)
+        _, info = L.decision_features(db, crit, src, d, type_rule=rule)
+        labels, vals = L.lookahead_labels(db, crit, src, d, info, 5, values=True,
+                                          type_rule=rule, downsize=ds)
         labels, vals = labels.cpu().numpy(), vals.cpu().numpy().reshape(-1, 5)
         for e in range(len(src)):
             w, caps, _ = b.instance(int(src[e]))
-            lab, ov = orc.rollout_label(w, caps, crit, int(d[e]))
+            lab, ov = orc.rollout_label(w, caps, crit, int(d[e]), type_rule=rule, downsize=ds)
             assert labels[e] == lab, (crit, e)
             assert np.array_equal(vals[e], ov), (crit, e)
 
