@@ -80,7 +80,9 @@ constexpr int kStaticLdsReserve = 1024;
 // source instance (their bin types are not written, so no pass follows)
 size_t plain_lds_per_wave(int slots, int max_items, bool wide, bool ext = false,
                           bool ds_loads = false);
-__host__ __device__ inline bool plain_ds_loads(const BatchArgs& a) { return a.downsize && a.src; }
+__host__ __device__ inline bool plain_ds_loads(const BatchArgs& a) {
+  return a.downsize && a.src;
+}
 size_t plain_lds_block_extra(bool learned);
 inline bool plain_ext(const BatchArgs& a) {
   return a.src || a.force || a.feat_out || a.info_out || a.type_rule == 2;

@@ -279,10 +279,14 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 // SPILL: the wavefront's arrays (keys, position->id map, suffix minima) sit
 // in a device region of per_wave bytes per instance instead of LDS, for
 // instances whose bins do not fit a workgroup's LDS (plain runs only).
-// BND: the bounded-active-bins code is compiled in (and taken when
+// OPT bit 0: the bounded-active-bins code is compiled in (and taken when
 // a.active_limit > 0); unbounded plain runs use the instantiation without it.
-template <int CRIT, typename K, bool EXT, bool SPILL, bool BND>
+// OPT bit 1 (extended runs): the per-bin loads of the downsized cost of
+// entries that name a source instance are kept; other runs go without them.
+template <int CRIT, typename K, bool EXT, bool SPILL, int OPT>
 __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per_wave) {
+  constexpr bool BND = (OPT & 1) != 0;
+  constexpr bool DSL = EXT && (OPT & 2) != 0;
   static_assert(!(EXT && SPILL), "decision hooks and the scorer run from LDS");
   using KT = KeyT<K>;
   using Pid = typename KT::Pid;
@@ -309,7 +313,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     hbuf = reinterpret_cast<float*>(hist + 16);
     bload = reinterpret_cast<int32_t*>(hbuf + 128);
   };
-  const bool dsl = EXT && plain_ds_loads(a);
+  const bool dsl = DSL && plain_ds_loads(a);
   if constexpr (!SPILL) carve(smem + model_bytes + (size_t)wave * (size_t)per_wave);
   if constexpr (EXT) {
     if (a.type_rule == 2) {
@@ -646,7 +650,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           const int id = nb;
           nb = uniform(nb + 1);
           if ((p & 255) == 0) fill_group(keys, p >> 8, lane, empty_key<CRIT, K>());
-          const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)p) : ((room << KT::SH) | (K)p);
+          const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)p)
+                                   : ((room << KT::SH) | (K)p);
           if (lane == (p & 63)) keys[kidx(p)] = key;
           if (lane == 0) pid[p] = (Pid)id;
           if (dsl && lane == 0) bload[id] = w;
@@ -687,12 +692,12 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
   }
 }
 
-template <int CRIT, typename K, bool EXT, bool SPILL, bool BND>
+template <int CRIT, typename K, bool EXT, bool SPILL, int OPT>
 hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
   const size_t lds = SPILL ? 0
                            : per_wave * (size_t)wpb +
                                  (EXT ? plain_lds_block_extra(a.type_rule == 2) : 0);
-  auto kern = k_plain<CRIT, K, EXT, SPILL, BND>;
+  auto kern = k_plain<CRIT, K, EXT, SPILL, OPT>;
   static bool raised = false;
   if (lds > 65536 && !raised) {
     hipError_t e = allow_max_dynamic_lds(kern);
@@ -706,29 +711,35 @@ hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hi
 
 template <int CRIT, typename K>
 hipError_t launch_sel(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
-  if (a.spill) return launch_one<CRIT, K, false, true, true>(a, wpb, per_wave, grid, s);
-  if (plain_ext(a)) return launch_one<CRIT, K, true, false, true>(a, wpb, per_wave, grid, s);
-  return a.active_limit > 0 ? launch_one<CRIT, K, false, false, true>(a, wpb, per_wave, grid, s)
-                            : launch_one<CRIT, K, false, false, false>(a, wpb, per_wave, grid, s);
+  if (a.spill) return launch_one<CRIT, K, false, true, 1>(a, wpb, per_wave, grid, s);
+  if (plain_ext(a))
+    return plain_ds_loads(a) ? launch_one<CRIT, K, true, false, 3>(a, wpb, per_wave, grid, s)
+                             : launch_one<CRIT, K, true, false, 1>(a, wpb, per_wave, grid, s);
+  return a.active_limit > 0 ? launch_one<CRIT, K, false, false, 1>(a, wpb, per_wave, grid, s)
+                            : launch_one<CRIT, K, false, false, 0>(a, wpb, per_wave, grid, s);
 }
 
 template <int CRIT, typename K>
-int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill, bool bounded) {
+int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill, bool bounded,
+              bool dsl) {
   int n = 0;
   hipError_t e;
   if (spill) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, true, true>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, true, 1>,
                                                      64 * wpb, 0);
   } else {
     const size_t lds = per_wave * (size_t)wpb + (ext ? plain_lds_block_extra(learned) : 0);
-    if (ext)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false, true>,
+    if (ext && dsl)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false, 3>,
+                                                       64 * wpb, lds);
+    else if (ext)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false, 1>,
                                                        64 * wpb, lds);
     else if (bounded)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false, true>,
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false, 1>,
                                                        64 * wpb, lds);
     else
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false, false>,
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, false, false, 0>,
                                                        64 * wpb, lds);
   }
   if (e != hipSuccess) return 1;
@@ -766,16 +777,16 @@ hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
 
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave) {
   const bool ext = plain_ext(a), learned = a.type_rule == 2, spill = a.spill != nullptr;
-  const bool bnd = a.active_limit > 0;
+  const bool bnd = a.active_limit > 0, dsl = plain_ds_loads(a);
   const size_t lw = lds_per_wave;
   if (!wide) {
-    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lw, ext, learned, spill, bnd);
-    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lw, ext, learned, spill, bnd);
-    return occupancy<WF, uint32_t>(wpb, lw, ext, learned, spill, bnd);
+    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl);
+    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl);
+    return occupancy<WF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl);
   }
-  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lw, ext, learned, spill, bnd);
-  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lw, ext, learned, spill, bnd);
-  return occupancy<WF, uint64_t>(wpb, lw, ext, learned, spill, bnd);
+  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl);
+  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl);
+  return occupancy<WF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl);
 }
 
 }  // namespace vsbpp

@@ -85,9 +85,11 @@ int32_t run_eager(vsbpp_plan* p, hipStream_t s) {
 }
 
 // Times every candidate shape on the batch itself and returns the fastest:
-// the least of five timed runs after a warm-up run, then the three best
-// candidates timed again the same way (launch times of one shape vary by a
-// few percent from run to run, so a single pass can rank close shapes wrongly).
+// the mean time of a burst of eight back-to-back runs after two warm-up
+// runs, then the three best candidates timed again the same way, keeping the
+// lower mean.  Back-to-back runs time a shape as a stream of launches meets
+// it (no idle gaps between runs); a single pass can still rank close shapes
+// wrongly, as launch times of one shape vary by a few percent.
 int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
   hipStream_t s = nullptr;
   if (hipStreamCreate(&s) != hipSuccess) return VSBPP_E_DEVICE;
@@ -97,28 +99,29 @@ int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
     return VSBPP_E_DEVICE;
   }
   int32_t rc = VSBPP_OK;
-  // least time of five runs of shape c, or a negative value when c does not
+  constexpr int kBurst = 8;
+  // mean time of a burst of shape c, or a negative value when c does not
   // apply to the batch
   auto time_cfg = [&](const vsbpp::LaunchCfg& c, float* out) -> int32_t {
     p->cfg = c;
-    int32_t r = run_eager(p, s);  // warm-up
-    if (r == VSBPP_E_SIZE || r == VSBPP_E_OPTION) {
-      *out = -1.0f;
-      return VSBPP_OK;
-    }
-    if (r != VSBPP_OK) return r;
-    float tmin = 1e30f;
-    for (int i = 0; i < 5; ++i) {
-      (void)hipEventRecord(e0, s);
-      r = run_eager(p, s);
-      (void)hipEventRecord(e1, s);
+    for (int i = 0; i < 2; ++i) {  // warm-up
+      const int32_t r = run_eager(p, s);
+      if (r == VSBPP_E_SIZE || r == VSBPP_E_OPTION) {
+        *out = -1.0f;
+        return VSBPP_OK;
+      }
       if (r != VSBPP_OK) return r;
-      if (hipEventSynchronize(e1) != hipSuccess) return VSBPP_E_DEVICE;
-      float t = 0.0f;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      tmin = std::min(tmin, t);
     }
-    *out = tmin;
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < kBurst; ++i) {
+      const int32_t r = run_eager(p, s);
+      if (r != VSBPP_OK) return r;
+    }
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return VSBPP_E_DEVICE;
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    *out = t / kBurst;
     return VSBPP_OK;
   };
   std::vector<std::pair<float, vsbpp::LaunchCfg>> timed;
