@@ -38,7 +38,17 @@ MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1602
 BIN_TESTS_PER_ITEM = {"FF": 235.1, "BF": 232.8, "WF": 339.5, "H1": 6.2, "H2": 574.0,
                       "FF+scorer": 194.9, "BF+scorer": 184.5, "WF+scorer": 290.3}
 SCORED_DECISIONS_PER_ITEM = {"FF+scorer": 0.4851, "BF+scorer": 0.4799, "WF+scorer": 0.5401}
-OPS_PER_BIN_TEST = 2          # form the room-after key, fold it into the min
+# VALU ops per bin test.  The P-system packers: compare, select and key per
+# bin of the packer (the per-unit work of the hot-path definition).  Plain
+# and scorer runs: room-after key and fold into the minimum; their per-unit
+# work is LDS traffic (below), reported next to the ALU figure.
+OPS_PER_BIN_TEST = {"H1": 3, "H2": 3}
+PLAIN_OPS_PER_BIN_TEST = 2
+# LDS bytes per item of the plain and scorer runs: a 16-bit room read per
+# live bin tested and a 16-bit room written
+LDS_BYTES_PER_BIN_TEST = 2
+LDS_BYTES_WRITTEN_PER_ITEM = 2
+LDS_PEAK = 256 * 128 * 2.4e9      # bytes/s: CUs x 128 B/clk x clock
 MLP_FMA_PER_DECISION = 16 * 64 + 64 * 64 + 64 * 5   # fused multiply-adds, one lane-op each
 ALU_PEAK = 256 * 4 * 16 * 2.4e9   # VALU lane-ops/s: CUs x SIMDs x lanes x clock
 # HBM bytes per launch of the current kernels on this workload, from rocprofv3
@@ -60,17 +70,28 @@ EXACT_OPS_PER_CANDIDATE = 2
 # HBM bytes per launch of the exact kernel on 16384 instances (rocprofv3,
 # profiles/exact_solver_m12.md); null for another batch size
 EXACT_HBM_BYTES_16384 = 14.33e6
-LDS_PEAK = 256 * 128 * 2.4e9      # bytes/s: CUs x 128 B/clk x clock
 
 
 def exact_candidates(m):
     return (3 ** m - 1) // 2
 
 
+def ops_per_bin_test(h):
+    return OPS_PER_BIN_TEST.get(h, PLAIN_OPS_PER_BIN_TEST)
+
+
 def ops_per_item(h):
     """Algorithmic VALU lane-ops per item placed by launch h."""
-    return (OPS_PER_BIN_TEST * BIN_TESTS_PER_ITEM[h]
+    return (ops_per_bin_test(h) * BIN_TESTS_PER_ITEM[h]
             + MLP_FMA_PER_DECISION * SCORED_DECISIONS_PER_ITEM.get(h, 0.0))
+
+
+def lds_bytes_per_item(h):
+    """Algorithmic LDS bytes per item of a plain or scorer run (None for the
+    P-system packers, whose bins live in registers and LDS as they pack)."""
+    if h in OPS_PER_BIN_TEST:
+        return None
+    return LDS_BYTES_PER_BIN_TEST * BIN_TESTS_PER_ITEM[h] + LDS_BYTES_WRITTEN_PER_ITEM
 
 
 def parse():
@@ -450,10 +471,13 @@ def main():
         per_kernel[h] = {"ms": round(kern_ms[h], 4),
                          "items_per_s": items / (kern_ms[h] / 1e3),
                          "alu_frac": achieved / ALU_PEAK}
+        lb_item = lds_bytes_per_item(h)
+        if lb_item is not None:
+            per_kernel[h]["lds_frac"] = lb_item * items / (kern_ms[h] / 1e3) / LDS_PEAK
     dom = max(heuristics, key=lambda h: kern_ms[h])
     ops_dom = ops_per_item(dom) * items
     achieved = ops_dom / (kern_ms[dom] / 1e3) / 1e12
-    work = f"({OPS_PER_BIN_TEST} ops x {BIN_TESTS_PER_ITEM[dom]} bin tests"
+    work = f"({ops_per_bin_test(dom)} ops x {BIN_TESTS_PER_ITEM[dom]} bin tests"
     if dom in SCORED_DECISIONS_PER_ITEM:
         work += (f" + {MLP_FMA_PER_DECISION} FMA x {SCORED_DECISIONS_PER_ITEM[dom]} scored "
                  "decisions")

@@ -18,5 +18,9 @@ def test_cpu_baseline_runs_every_launch():
 
 def test_work_per_item_counts_the_network():
     for h in bench.LEARNED:
-        assert bench.ops_per_item(h) > bench.OPS_PER_BIN_TEST * bench.BIN_TESTS_PER_ITEM[h]
-    assert bench.ops_per_item("BF") == bench.OPS_PER_BIN_TEST * bench.BIN_TESTS_PER_ITEM["BF"]
+        assert bench.ops_per_item(h) > bench.ops_per_bin_test(h) * bench.BIN_TESTS_PER_ITEM[h]
+    assert bench.ops_per_item("BF") == 2 * bench.BIN_TESTS_PER_ITEM["BF"]
+    # the P-system packers: compare, select and key per bin of the packer
+    assert bench.ops_per_item("H2") == 3 * bench.BIN_TESTS_PER_ITEM["H2"]
+    assert bench.lds_bytes_per_item("H2") is None
+    assert bench.lds_bytes_per_item("BF") == 2 * bench.BIN_TESTS_PER_ITEM["BF"] + 2

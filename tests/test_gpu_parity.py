@@ -143,6 +143,26 @@ def test_large_single_instances(V, orc):
         assert np.array_equal(g.assignment, o.assignment), h
 
 
+def test_largest_item_counts(V, orc):
+    """More than 65535 items (64-bit keys by item count, bins in a device
+    region for the plain heuristics) and 10^5 items for H1/H2, with the
+    paper's small weights over bins {300, 200, 100} and with weights spread
+    over the largest bin."""
+    rng = np.random.default_rng(510)
+    small = rng.integers(1, 21, size=100000).astype(np.int32)
+    spread = rng.integers(1, 1001, size=70000).astype(np.int32)
+    for h, w, caps in (("FF", spread, [1000, 700, 300]), ("BF", small[:70000], [300, 200, 100]),
+                       ("WF", spread, [1000, 700, 300]), ("H1", small, [300, 200, 100]),
+                       ("H2", small, [300, 200, 100]), ("H2", spread, [1000, 700, 300])):
+        print("largest", h, w.size, flush=True)
+        caps = np.array(caps, dtype=np.int32)
+        g = V.pack(w, caps, h, seed=11)
+        o = orc.pack(w, caps, h, seed=11)
+        assert g.cost == o.cost and g.nbins == o.nbins, h
+        assert np.array_equal(g.assignment, o.assignment), h
+        assert np.array_equal(g.bin_types, o.bin_types), h
+
+
 def test_determinism_and_batch_position(V, orc):
     rng = np.random.default_rng(600)
     b = inputs.random_batch(rng, 64, 1, 500)
