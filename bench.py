@@ -55,9 +55,9 @@ ALU_PEAK = 256 * 4 * 16 * 2.4e9   # VALU lane-ops/s: CUs x SIMDs x lanes x clock
 # FETCH_SIZE (x2: it counts half of a known-size copy's reads) and WRITE_SIZE
 # (x1) -- profiles/pack_kernels_uniform_batch.md.  Taken again whenever a
 # kernel changes (a launch without a current figure reports null).
-MEASURED_HBM_BYTES = {"H2": 45.38e6, "FF": 50.73e6, "BF": 51.35e6, "WF": 51.70e6,
+MEASURED_HBM_BYTES = {"H2": 45.05e6, "FF": 50.47e6, "BF": 50.57e6, "WF": 51.25e6,
                       "H1": 47.23e6, "FF+scorer": 48.33e6, "BF+scorer": 48.42e6,
-                      "WF+scorer": 49.29e6}
+                      "WF+scorer": 49.30e6}
 
 
 # Exact solver leg (outside the step): instances of the uniform distribution
@@ -211,6 +211,15 @@ def exact_leg(V, torch, n_inst, steps, warmup, cpu_sample):
     gap = {}
     outs, models, plans = make_plans(V, torch, db, HEURISTICS + LEARNED, graph=False,
                                      autotune=False)
+    for c in ("FF", "BF", "WF"):
+        o = V.DeviceBatch.__new__(V.DeviceBatch)
+        o.__dict__.update(db.__dict__)
+        o.assignment = torch.empty_like(db.assignment)
+        o.bin_types = torch.empty_like(db.bin_types)
+        o.nbins = torch.empty_like(db.nbins)
+        o.cost = torch.empty_like(db.cost)
+        outs[f"{c} largest+downsize"] = o
+        plans[f"{c} largest+downsize"] = V.Plan(o, c, type_rule=V.TYPE_LARGEST, downsize=True)
     for h, p in plans.items():
         p.run(stream)
         torch.cuda.synchronize()

@@ -681,41 +681,42 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
             const uint32_t k2 = (uint32_t)(v.z + x) & msk, k3 = (uint32_t)(v.w + x) & msk;
             const uint32_t k4 = (uint32_t)(u.x + x) & msk, k5 = (uint32_t)(u.y + x) & msk;
             const uint32_t k6 = (uint32_t)(u.z + x) & msk, k7 = (uint32_t)(u.w + x) & msk;
-            best = min(best, min(k0, k1));
-            best = min(best, min(k2, k3));
-            best = min(best, min(k4, k5));
-            best = min(best, min(k6, k7));
+            // one three-way minimum per two keys
+            best = min(min(best, k0), k1);
+            best = min(min(best, k2), k3);
+            best = min(min(best, k4), k5);
+            best = min(min(best, k6), k7);
           }
-          int b, type;
-          int32_t room, cap;
-          if (best < (1u << 25)) {
-            b = (int)((best >> 5) & 31u);
-            type = (int)(best & 31u);
-            const int32_t word = myA[slot_word(b, stride)];
-            cap = s_caps[type];
-            room = (word >> 10) - w;
-          } else {
-            // nothing fits: open the item's bin type (resolved with its chunk)
-            type = tc >> 16;
-            cap = tc & 0xFFFF;
-            b = nb++;
-            room = cap - w;
-          }
+          // The chosen bin, or a new bin of the item's type (resolved with
+          // its chunk) at the next free slot.  Both cases run the same
+          // straight-line code: permutations of a wave take different
+          // branches, and selects cost less than both branch bodies.
+          const bool found = best < (1u << 25);
+          const int b = found ? (int)((best >> 5) & 31u) : nb;
+          const int type = found ? (int)(best & 31u) : (tc >> 16);
+          const int sw = slot_word(b, stride);
+          const int32_t word = myA[sw];   // a free slot holds an empty bin word
+          const int32_t cap = s_caps[type];
+          const int32_t room = (found ? (word >> 10) : cap) - w;
+          nb += found ? 0 : 1;
           const int32_t tag = (b << 5) | type;
-          myA[slot_word(b, stride)] = (room << 10) | tag;
-          myW[slot_word(b, stride)] = ((kR5 - room) << 10) | tag;
-          if (!((used >> b) & 1u)) {
-            used |= 1u << b;
-            cost += cap;
-          }
-          // Rule 5: a bin at least half full divides once
-          if (!((div >> b) & 1u) && 2 * (cap - room) >= cap) {
-            div |= 1u << b;
-            const int nbn = nb++;
-            const int32_t tagn = (nbn << 5) | type;
-            myA[slot_word(nbn, stride)] = (cap << 10) | tagn;
-            myW[slot_word(nbn, stride)] = ((kR5 - cap) << 10) | tagn;
-          }
+          myA[sw] = (room << 10) | tag;
+          myW[sw] = ((kR5 - room) << 10) | tag;
+          cost += ((used >> b) & 1u) ? 0 : cap;
+          used |= 1u << b;
+          // Rule 5: a bin at least half full divides once, adding an empty bin
+          // of its type at the next free slot.  Without a division that slot
+          // is rewritten with the empty word it already holds (room 0, type
+          // 0), which no scan picks.
+          const bool split = !((div >> b) & 1u) && 2 * (cap - room) >= cap;
+          div |= split ? (1u << b) : 0u;
+          const int nbn = nb;
+          nb += split ? 1 : 0;
+          const int swn = slot_word(nbn, stride);
+          const int32_t capn = split ? cap : 0;
+          const int32_t tagn = (nbn << 5) | (split ? type : 0);
+          myA[swn] = (capn << 10) | tagn;
+          myW[swn] = ((kR5 - capn) << 10) | tagn;
           locs |= (uint32_t)b << (5 * d);
         }
         key = ((uint32_t)cost << 10) | (uint32_t)r;

@@ -89,7 +89,9 @@ int32_t run_eager(vsbpp_plan* p, hipStream_t s) {
 // runs, then the three best candidates timed again the same way, keeping the
 // lower mean.  Back-to-back runs time a shape as a stream of launches meets
 // it (no idle gaps between runs); a single pass can still rank close shapes
-// wrongly, as launch times of one shape vary by a few percent.
+// wrongly, as launch times of one shape vary by a few percent; among shapes
+// within 2% of the fastest the one with the most wavefronts per workgroup
+// is kept.
 int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
   hipStream_t s = nullptr;
   if (hipStreamCreate(&s) != hipSuccess) return VSBPP_E_DEVICE;
@@ -146,6 +148,13 @@ int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
         return x.first < y.first;
       });
       *best = it->second;
+      // shapes within 2% of the fastest are a tie on this measurement: take
+      // the one with the most wavefronts per workgroup (fewer, larger
+      // workgroups, which a stream of other launches dispatches faster)
+      for (const auto& tc : timed)
+        if (tc.first <= it->first * 1.02f && tc.second.mode == best->mode &&
+            tc.second.lpt == best->lpt && tc.second.wpb > best->wpb)
+          *best = tc.second;
     }
   }
   const bool found = !timed.empty();
