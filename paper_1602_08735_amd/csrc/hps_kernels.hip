@@ -527,27 +527,32 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 // ---------------------------------------------------------------------------
 // Second heuristic with 32-bit bin words (B_1 <= 32767), the common case.
 //
-// Bin b of thread t is two words, in arrays A and W of the workgroup's LDS at
-// (b >> 2) * 4*blockDim + 4*t + (b & 3), with the bin's type k < 16:
-//   A = room << 10 | b << 5 | k,   W = (R - room) << 10 | b << 5 | k,
-//   R = 32767.
-// The candidate key of weight w in bin b (W10 = w << 10):
+// Bin b of thread t is one word of the workgroup's LDS array A, at
+// (b >> 2) * 4*blockDim + 4*t + (b & 3), with the bin's type k < 32:
+//   A = room << 10 | b << 5 | k.
+// The candidate key of weight w in bin b (W10 = w << 10, R = 32767):
 //   BF: A - W10                  least room after, then lowest b; a bin the
 //                                item does not fit wraps to >= 2^31
-//   WF: W + W10                  most room after, then lowest b; no fit
-//                                >= 2^25
+//   WF: (A ^ ~1023) + XW         = (R - room + w) << 10 | b << 5 | k: most
+//                                room after, then lowest b; no fit >= 2^25.
+//                                The xor turns room into 2^22-1 - room and
+//                                XW = (R + w - (2^22-1)) << 10 shifts it back
 //   FF: (A - W10) & (2^31|1023)  b << 5 | k, or >= 2^31
-// Every fitting key is below 2^25 and every other one is not, so a placement
-// is one add, one mask and a minimum per bin, over the array its criterion
-// reads, and the least key also names the bin's type.  Slots without a bin
-// hold room 0 (A = b << 5, W = R << 10 | b << 5): nothing fits them.  The
-// used-bin mask and the cost are kept as the items go, so a packer needs no
-// final pass over its bins.
+// All three are ((A ^ s) + x) & mask, one xor-add and one mask per bin with
+// per-lane s, x and mask.  Every fitting key is below 2^25 and every other
+// one is not, so the least key also names the bin's type.  Slots without a
+// bin hold room 0 (A = b << 5): nothing fits them.  The used-bin mask and
+// the cost are kept as the items go, so a packer needs no final pass over
+// its bins.
 //
 // Rule-1 positions, their weights and the bin each item opens when nothing
 // fits are resolved a chunk of rounds at a time by the whole workgroup, and
-// every packer starts from a per-instance template of its Rule-2 bins.  A round (spr subsets) needs two barriers: one for the group
-// minimum, one before the winners' results are read.
+// every packer starts from a per-instance template of its Rule-2 bins.  A
+// round (spr subsets) needs two barriers: one for the group minimum, one
+// before the bin counts of all groups are read.  The winner's own wave then
+// writes its assignment and bin types, one lane per item and one per bin,
+// reading the winner's bins from LDS: in program order before that wave's
+// next round overwrites them, and no other wave writes them.
 // ---------------------------------------------------------------------------
 constexpr int32_t kR5 = 32767;
 
@@ -566,18 +571,13 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   const int spr = B / group;  // subsets per round
   const int stride = 4 * B;
   int32_t* arrA = reinterpret_cast<int32_t*>(smem);
-  int32_t* arrW = arrA + (size_t)nbslots * B;
-  int32_t* tmplA = arrW + (size_t)nbslots * B;  // [nbslots]
-  int32_t* tmplW = tmplA + nbslots;             // [nbslots]
-  int32_t* s_ci = tmplW + nbslots;              // [B] chunk items
+  int32_t* tmplA = arrA + (size_t)nbslots * B;  // [nbslots]
+  int32_t* s_ci = tmplA + nbslots;              // [B] chunk items
   int32_t* s_cw = s_ci + B;                     // [B] chunk weights
   int32_t* s_ct = s_cw + B;                     // [B] type << 16 | capacity of a new bin
-  int32_t* s_loc = s_ct + B;                    // [spr][6] canonical local ids
-  int32_t* s_typ = s_loc + spr * kMaxSubset;    // [spr][6] types of used bins
-  int32_t* s_u = s_typ + spr * kMaxSubset;      // [spr] used bins
+  int32_t* s_u = s_ct + B;                      // [spr] used bins
   int32_t* s_cst = s_u + spr;                   // [spr] subset cost
   int32_t* myA = arrA + 4 * tid;
-  int32_t* myW = arrW + 4 * tid;
   const int g = tid / group, r = tid - g * group;
   const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
 
@@ -604,9 +604,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
     // Rule 2 template: bins 0..n-1 empty with their capacity as room
     if (tid < nbslots) {
       const int32_t room = tid < n ? s_caps[tid] : 0;
-      const int32_t tag = (tid << 5) | (tid < n ? tid : 0);
-      tmplA[tid] = (room << 10) | tag;
-      tmplW[tid] = ((kR5 - room) << 10) | tag;
+      tmplA[tid] = (room << 10) | (tid << 5) | (tid < n ? tid : 0);
     }
     const uint64_t seed = inst_seed(a, inst);
     Rule1Perm perm;
@@ -651,10 +649,8 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       uint32_t used = 0, locs = 0;
       int32_t cost = 0;
       if (active) {
-        for (int gi = 0; gi < (nbslots >> 2); ++gi) {
+        for (int gi = 0; gi < (nbslots >> 2); ++gi)
           *reinterpret_cast<int4*>(myA + gi * stride) = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
-          *reinterpret_cast<int4*>(myW + gi * stride) = *reinterpret_cast<const int4*>(tmplW + 4 * gi);
-        }
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
         uint64_t st = ck + ((((uint64_t)I * (uint64_t)P + (uint64_t)r) * (uint64_t)S) + 1ull) * kGolden;
         uint32_t div = 0;
@@ -665,9 +661,12 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const int32_t tc = s_ct[lq + d];
           const int crit = a.force_crit >= 0 ? a.force_crit : criterion_at_state(st);
           st += kGolden;
-          const int32_t w10 = w << 10;
-          const int32_t* base = crit == WF ? myW : myA;
-          const int32_t x = crit == WF ? w10 : -w10;
+          // x = XW or -W10, as (W10 ^ nm) + ad without a branch
+          const bool wf = crit == WF;
+          const uint32_t sx = wf ? 0xFFFFFC00u : 0u;
+          const uint32_t nm = wf ? 0u : 0xFFFFFFFFu;
+          const uint32_t ad = wf ? (uint32_t)(kR5 - 0x3FFFFF) << 10 : 1u;
+          const uint32_t x = (((uint32_t)w << 10) ^ nm) + ad;
           const uint32_t msk = crit == FF ? 0x800003FFu : 0xFFFFFFFFu;
           // groups that can hold bins after t placements (each adds <= 2)
           const int ng = (min(nbslots, n + 2 * t) + 3) >> 2;
@@ -675,12 +674,12 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           uint32_t best = 0xFFFFFFFFu;
           for (int gi = 0; gi < ng; gi += 2) {
             const int gj = gi + 1 < ng ? gi + 1 : gi;
-            const int4 v = *reinterpret_cast<const int4*>(base + gi * stride);
-            const int4 u = *reinterpret_cast<const int4*>(base + gj * stride);
-            const uint32_t k0 = (uint32_t)(v.x + x) & msk, k1 = (uint32_t)(v.y + x) & msk;
-            const uint32_t k2 = (uint32_t)(v.z + x) & msk, k3 = (uint32_t)(v.w + x) & msk;
-            const uint32_t k4 = (uint32_t)(u.x + x) & msk, k5 = (uint32_t)(u.y + x) & msk;
-            const uint32_t k6 = (uint32_t)(u.z + x) & msk, k7 = (uint32_t)(u.w + x) & msk;
+            const uint4 v = *reinterpret_cast<const uint4*>(myA + gi * stride);
+            const uint4 u = *reinterpret_cast<const uint4*>(myA + gj * stride);
+            const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
+            const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
+            const uint32_t k4 = ((u.x ^ sx) + x) & msk, k5 = ((u.y ^ sx) + x) & msk;
+            const uint32_t k6 = ((u.z ^ sx) + x) & msk, k7 = ((u.w ^ sx) + x) & msk;
             // one three-way minimum per two keys
             best = min(min(best, k0), k1);
             best = min(min(best, k2), k3);
@@ -699,9 +698,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const int32_t cap = s_caps[type];
           const int32_t room = (found ? (word >> 10) : cap) - w;
           nb += found ? 0 : 1;
-          const int32_t tag = (b << 5) | type;
-          myA[sw] = (room << 10) | tag;
-          myW[sw] = ((kR5 - room) << 10) | tag;
+          myA[sw] = (room << 10) | (b << 5) | type;
           cost += ((used >> b) & 1u) ? 0 : cap;
           used |= 1u << b;
           // Rule 5: a bin at least half full divides once, adding an empty bin
@@ -714,9 +711,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           nb += split ? 1 : 0;
           const int swn = slot_word(nbn, stride);
           const int32_t capn = split ? cap : 0;
-          const int32_t tagn = (nbn << 5) | (split ? type : 0);
-          myA[swn] = (capn << 10) | tagn;
-          myW[swn] = ((kR5 - capn) << 10) | tagn;
+          myA[swn] = (capn << 10) | (nbn << 5) | (split ? type : 0);
           locs |= (uint32_t)b << (5 * d);
         }
         key = ((uint32_t)cost << 10) | (uint32_t)r;
@@ -728,19 +723,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       gm = 0xFFFFFFFFu;
       for (int i = 0; i < wpg; ++i) gm = min(gm, s_wmin[g * wpg + i]);
       if (active && key == gm) {
-        for (int d = 0; d < k; ++d) {
-          const int b = (int)((locs >> (5 * d)) & 31u);
-          s_loc[g * kMaxSubset + d] = (int)__popc(used & ((1u << b) - 1u));
-        }
-        uint32_t uu = used;
-        int rr = 0;
-        while (uu) {
-          const int b = __builtin_ctz(uu);
-          uu &= uu - 1;
-          s_typ[g * kMaxSubset + rr] = myA[slot_word(b, stride)] & 31;
-          ++rr;
-        }
-        s_u[g] = rr;
+        s_u[g] = (int32_t)__popc(used);
         s_cst[g] = cost;
       }
       if (r == 0 && k == 0) {
@@ -759,8 +742,22 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       }
       carry += total;
       cost_acc += round_cost;
-      if (r < k) a.assign[off + s_ci[lq + r]] = before + s_loc[g * kMaxSubset + r];
-      if (k > 0 && r < s_u[g]) a.types[off + before + r] = s_typ[g * kMaxSubset + r];
+      // the winner's wave writes its result: lane d the item at subset
+      // position d, lane b the type of bin slot b if used
+      const int wr = (int)(gm & 1023u);  // the winning rank
+      if (k > 0 && wave == g * wpg + (wr >> 6)) {
+        const uint32_t wused = readlane(used, wr & 63);
+        const uint32_t wlocs = readlane(locs, wr & 63);
+        if (lane < k) {
+          const int b = (int)((wlocs >> (5 * lane)) & 31u);
+          a.assign[off + s_ci[lq + lane]] = before + (int)__popc(wused & ((1u << b) - 1u));
+        }
+        if (lane < 32 && ((wused >> lane) & 1u)) {
+          const int32_t* winA = arrA + 4 * (g * group + wr);
+          a.types[off + before + (int)__popc(wused & ((1u << lane) - 1u))] =
+              winA[slot_word(lane, stride)] & 31;
+        }
+      }
     }
     if (tid == 0) {
       a.nbins[inst] = carry;
@@ -826,9 +823,8 @@ int h2_group(int s2) {
 
 size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k) {
   const int spr = block / group;
-  if (k == H2Kernel::kSlim)  // bin arrays A and W, templates, chunk, per-subset results
-    return 4 * (2 * (size_t)nbslots * block + 2 * (size_t)nbslots + 3 * (size_t)block +
-                (size_t)spr * (2 * kMaxSubset + 2));
+  if (k == H2Kernel::kSlim)  // bin array A, its template, chunk, per-subset results
+    return 4 * ((size_t)nbslots * block + (size_t)nbslots + 3 * (size_t)block + 2 * (size_t)spr);
   return (size_t)block * (k == H2Kernel::kWide ? 2 : 1) * 4 * (size_t)nbslots +
          (size_t)spr * (4 * kMaxSubset * 4 + 2 * 4) + (size_t)spr * 8;
 }

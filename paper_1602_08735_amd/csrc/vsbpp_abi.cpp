@@ -149,8 +149,9 @@ int h_nbslots(int heuristic, const BatchArgs& a) {
   return round_up(a.max_types + 2 * (heuristic == VSBPP_H1 ? a.s1 : a.s2), 4);
 }
 
-// the H2 kernel for a workgroup size: two words per bin when they fit the
-// workgroup's LDS, else one packed word (64-bit bins for wide batches)
+// the H2 kernel for a workgroup size: the slim kernel (32-bit bin words plus
+// a chunk of resolved positions) when it fits the workgroup's LDS, else the
+// packed one (64-bit bins for wide batches)
 H2Kernel h2_kernel(const BatchArgs& a, int block) {
   if (is_wide(a)) return H2Kernel::kWide;
   const size_t budget = (size_t)(device_info().max_lds_block - kStaticLdsReserve);
