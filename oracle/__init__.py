@@ -113,6 +113,8 @@ def lib():
         L.orc_stream_key.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_criterion.restype = ctypes.c_int32
         L.orc_criterion.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_criterion_digit.restype = ctypes.c_int32
+        L.orc_criterion_digit.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32]
         L.orc_perm.restype = ctypes.c_int32
         L.orc_perm.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]
         L.orc_pack.restype = ctypes.c_int32
@@ -176,6 +178,11 @@ def stream_key(seed: int, stream: int) -> int:
 
 def criterion(key: int, counter: int) -> int:
     return int(lib().orc_criterion(key & (2**64 - 1), counter))
+
+
+def criterion_digit(key: int, counter: int, t: int) -> int:
+    """The second heuristic's draw: digit t+1 (base 3) of output `counter`."""
+    return int(lib().orc_criterion_digit(key & (2**64 - 1), counter, t))
 
 
 def perm(seed: int, m: int) -> np.ndarray:

@@ -40,6 +40,18 @@ int32_t orc_criterion(uint64_t stream_key, uint64_t counter) {
   return (int32_t)((hi * 3u) >> 32);
 }
 
+/* Rule 3 for the second heuristic (Section 6.4): each permutation packing
+ * takes one generator output, counter I*S! + r, and its t-th placement the
+ * (t+1)-th base-3 digit of h/2^32, h = the output's high 32 bits:
+ * floor(3^(t+1) * h / 2^32) mod 3.  For t < 6, 3^(t+1) * h < 2^64.  Every
+ * tuple of the first k <= 6 digits has probability 3^-k up to 3^k/2^32. */
+int32_t orc_criterion_digit(uint64_t stream_key, uint64_t counter, int32_t t) {
+  uint64_t h = orc_splitmix64(stream_key, counter) >> 32;
+  uint64_t p = 3;
+  for (int32_t i = 0; i < t; ++i) p *= 3;
+  return (int32_t)(((p * h) >> 32) % 3u);
+}
+
 /* purposes of the generator streams */
 #define STREAM_RULE1 1u
 #define STREAM_H1 2u
@@ -566,7 +578,7 @@ static void nth_permutation(int64_t r, int32_t k, int32_t* out) {
  * rank r) is packed by its own packer with Rules 2-6; the subset keeps the
  * permutation of least cost, the lowest rank on ties; the instance cost is
  * the sum over subsets.  Criterion of placement t of permutation r of subset
- * I: counter (I*S! + r)*S + t of the H2 stream. */
+ * I: digit t of output I*S! + r of the H2 stream (orc_criterion_digit). */
 static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                       const orc_opts* o, int32_t* assign, int32_t* types,
                       int64_t* cost, orc_stats* st) {
@@ -596,7 +608,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
       for (int32_t t = 0; t < k; ++t) {
         int32_t c = o->force_crit >= 0
                         ? o->force_crit
-                        : orc_criterion(ck, (uint64_t)(((int64_t)I * P + r) * S + t));
+                        : orc_criterion_digit(ck, (uint64_t)((int64_t)I * P + r), t);
         place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL);
       }
       int64_t c = packer_cost(&p, caps);
@@ -615,7 +627,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
     for (int32_t t = 0; t < k; ++t) {
       int32_t c = o->force_crit >= 0
                       ? o->force_crit
-                      : orc_criterion(ck, (uint64_t)(((int64_t)I * P + best_r) * S + t));
+                      : orc_criterion_digit(ck, (uint64_t)((int64_t)I * P + best_r), t);
       placed_items[t] = items[order[t]];
       local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, 0, NULL, NULL, NULL);
     }

@@ -93,6 +93,7 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t k);
 uint64_t orc_stream_key(uint64_t seed, uint64_t stream);
 /* criterion draw in {0,1,2} = {FF,BF,WF} with equal probabilities */
 int32_t orc_criterion(uint64_t stream_key, uint64_t counter);
+int32_t orc_criterion_digit(uint64_t stream_key, uint64_t counter, int32_t t);
 /* pseudo-random permutation of [0,m): the item at position q (Rule 1) */
 int32_t orc_perm(uint64_t seed, int32_t m, int32_t q);
 

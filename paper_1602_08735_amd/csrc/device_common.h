@@ -125,18 +125,17 @@ __device__ __forceinline__ int draw_criterion(uint64_t key, uint64_t counter) {
   return (int)((hi * 3ull) >> 32);
 }
 
-// The same draw from the generator's state s = key + (counter+1)*gamma, so a
-// run of consecutive counters advances s by gamma.  Only the high word of the
-// output is needed: hi32(x ^ (x >> 31)) = hi32(x) ^ (hi32(x) >> 31), and
-// floor(3h / 2^32) = [h >= ceil(2^32/3)] + [h >= ceil(2^33/3)].
-__device__ __forceinline__ int criterion_at_state(uint64_t s) {
-  s ^= s >> 30;
-  s *= 0xbf58476d1ce4e5b9ull;
-  s ^= s >> 27;
-  s *= 0x94d049bb133111ebull;
-  uint32_t hi = (uint32_t)(s >> 32);
-  hi ^= hi >> 31;
-  return (hi >= 0x55555556u ? 1 : 0) + (hi >= 0xAAAAAAABu ? 1 : 0);
+// The second heuristic's draws: one output per permutation packing, its high
+// word h; the criterion of placement t is digit t+1 of h / 2^32 in base 3.
+// With u = h: criterion = floor(3u / 2^32), then u = 3u mod 2^32, per
+// placement (digits_next).
+__device__ __forceinline__ uint32_t digits_word(uint64_t key, uint64_t counter) {
+  return (uint32_t)(splitmix64(key, counter) >> 32);
+}
+__device__ __forceinline__ int digits_next(uint32_t& u) {
+  const int c = (int)__umulhi(u, 3u);
+  u *= 3u;
+  return c;
 }
 
 // Rule 1 distribution: keyed permutation of [0,m) from a 4-round balanced

@@ -456,13 +456,12 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
       if (active) {
         pk.init(s_caps, n, nbslots);
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
+        uint32_t cu = digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
           const int32_t w = s_w[g * kMaxSubset + d];
-          const int crit = a.force_crit >= 0
-                               ? a.force_crit
-                               : draw_criterion(ck, ((uint64_t)I * (uint64_t)P + (uint64_t)r) *
-                                                            (uint64_t)S + (uint64_t)t);
+          const int drawn = digits_next(cu);
+          const int crit = a.force_crit >= 0 ? a.force_crit : drawn;
           const int b = pk.place(w, crit, min(nbslots, n + 2 * t), s_caps, n, a.type_rule);
           locs |= (uint64_t)b << (6 * d);
         }
@@ -652,15 +651,15 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
         for (int gi = 0; gi < (nbslots >> 2); ++gi)
           *reinterpret_cast<int4*>(myA + gi * stride) = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
-        uint64_t st = ck + ((((uint64_t)I * (uint64_t)P + (uint64_t)r) * (uint64_t)S) + 1ull) * kGolden;
+        uint32_t cu = digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
         uint32_t div = 0;
         int nb = n;
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
           const int32_t w = s_cw[lq + d];
           const int32_t tc = s_ct[lq + d];
-          const int crit = a.force_crit >= 0 ? a.force_crit : criterion_at_state(st);
-          st += kGolden;
+          const int drawn = digits_next(cu);
+          const int crit = a.force_crit >= 0 ? a.force_crit : drawn;
           // x = XW or -W10, as (W10 ^ nm) + ad without a branch
           const bool wf = crit == WF;
           const uint32_t sx = wf ? 0xFFFFFC00u : 0u;

@@ -39,6 +39,36 @@ def test_criterion_stream_independence(orc):
     assert a != b and a != c
 
 
+def test_h2_criterion_digits_of_known_outputs(orc):
+    """The second heuristic's draw t from output k is digit t+1 of h/2^32 in
+    base 3, h the high word of the published known-answer output k (exact
+    rational expansion)."""
+    from fractions import Fraction
+
+    g = golden("splitmix64_known_answers.json")
+    for k, x in enumerate(g["outputs"]):
+        frac = Fraction(int(x) >> 32, 2**32)
+        for t in range(6):
+            frac *= 3
+            d = int(frac)
+            frac -= d
+            assert orc.criterion_digit(g["seed"], k, t) == d, (k, t)
+
+
+def test_h2_criterion_digits_joint_uniform(orc):
+    """Rule 3 per placement: the first five digits of one output are five
+    independent equiprobable criteria (chi-square over the 243 tuples)."""
+    from scipy.stats import chi2
+
+    key = orc.stream_key(777, 3)
+    per = 100
+    cells = [sum(orc.criterion_digit(key, k, t) * 3**t for t in range(5))
+             for k in range(243 * per)]
+    counts = np.bincount(cells, minlength=243)
+    stat = float(((counts - per) ** 2 / per).sum())
+    assert stat < chi2.ppf(0.999, 242)
+
+
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 7, 10, 16, 17, 100, 1000, 1023, 1024, 1025, 4097])
 def test_rule1_permutation_is_bijection(orc, m):
     for seed in (0, 1, 99):
