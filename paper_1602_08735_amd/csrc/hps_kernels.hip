@@ -555,9 +555,11 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 // ---------------------------------------------------------------------------
 constexpr int32_t kR5 = 32767;
 
-// word of slot b; (b >> 2) * stride < 2^24 and stride is a multiple of 4
-__device__ __forceinline__ int slot_word(int b, int stride) {
-  return (int)(__umul24((unsigned)(b >> 2), (unsigned)stride) | (unsigned)(b & 3));
+// slot b of the packer whose slot 0 is `first`: (b >> 2) * stride + (b & 3)
+// words on, i.e. b + (b >> 2) * step words with step = stride - 4
+// (< 2^24 for the largest workgroup)
+__device__ __forceinline__ int32_t* slot_at(int32_t* first, int b, unsigned step) {
+  return first + (int)(__umul24((unsigned)(b >> 2), step) + (unsigned)b);
 }
 
 __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int group) {
@@ -569,6 +571,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   const int tid = threadIdx.x, B = blockDim.x;
   const int spr = B / group;  // subsets per round
   const int stride = 4 * B;
+  const unsigned step = (unsigned)stride - 4u;
   int32_t* arrA = reinterpret_cast<int32_t*>(smem);
   int32_t* tmplA = arrA + (size_t)nbslots * B;  // [nbslots]
   int32_t* s_ci = tmplA + nbslots;              // [B] chunk items
@@ -648,11 +651,12 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       uint32_t used = 0, locs = 0;
       int32_t cost = 0;
       if (active) {
+        // bins not used yet and bins not divided yet, one bit per slot
+        uint32_t nused = 0xFFFFFFFFu, nodiv = 0xFFFFFFFFu;
         for (int gi = 0; gi < (nbslots >> 2); ++gi)
           *reinterpret_cast<int4*>(myA + gi * stride) = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
         uint32_t cu = digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
-        uint32_t div = 0;
         int nb = n;
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
@@ -669,12 +673,12 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const uint32_t msk = crit == FF ? 0x800003FFu : 0xFFFFFFFFu;
           // groups that can hold bins after t placements (each adds <= 2)
           const int ng = (min(nbslots, n + 2 * t) + 3) >> 2;
-          // two groups per LDS round trip (an odd last group is read twice)
+          // two groups per LDS round trip, then an odd last group alone
           uint32_t best = 0xFFFFFFFFu;
-          for (int gi = 0; gi < ng; gi += 2) {
-            const int gj = gi + 1 < ng ? gi + 1 : gi;
+          int gi = 0;
+          for (; gi + 1 < ng; gi += 2) {
             const uint4 v = *reinterpret_cast<const uint4*>(myA + gi * stride);
-            const uint4 u = *reinterpret_cast<const uint4*>(myA + gj * stride);
+            const uint4 u = *reinterpret_cast<const uint4*>(myA + (gi + 1) * stride);
             const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
             const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
             const uint32_t k4 = ((u.x ^ sx) + x) & msk, k5 = ((u.y ^ sx) + x) & msk;
@@ -685,6 +689,13 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
             best = min(min(best, k4), k5);
             best = min(min(best, k6), k7);
           }
+          if (gi < ng) {
+            const uint4 v = *reinterpret_cast<const uint4*>(myA + gi * stride);
+            const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
+            const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
+            best = min(min(best, k0), k1);
+            best = min(min(best, k2), k3);
+          }
           // The chosen bin, or a new bin of the item's type (resolved with
           // its chunk) at the next free slot.  Both cases run the same
           // straight-line code: permutations of a wave take different
@@ -692,27 +703,29 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const bool found = best < (1u << 25);
           const int b = found ? (int)((best >> 5) & 31u) : nb;
           const int type = found ? (int)(best & 31u) : (tc >> 16);
-          const int sw = slot_word(b, stride);
-          const int32_t word = myA[sw];   // a free slot holds an empty bin word
+          int32_t* const pb = slot_at(myA, b, step);
+          const int32_t word = *pb;  // a free slot holds an empty bin word
           const int32_t cap = s_caps[type];
           const int32_t room = (found ? (word >> 10) : cap) - w;
           nb += found ? 0 : 1;
-          myA[sw] = (room << 10) | (b << 5) | type;
-          cost += ((used >> b) & 1u) ? 0 : cap;
-          used |= 1u << b;
-          // Rule 5: a bin at least half full divides once, adding an empty bin
-          // of its type at the next free slot.  Without a division that slot
-          // is rewritten with the empty word it already holds (room 0, type
-          // 0), which no scan picks.
-          const bool split = !((div >> b) & 1u) && 2 * (cap - room) >= cap;
-          div |= split ? (1u << b) : 0u;
+          *pb = (room << 10) | (b << 5) | type;
+          // a bin's first item adds its capacity to the cost (bit b of nused
+          // sign-extended: all ones or zero)
+          cost += cap & __builtin_amdgcn_sbfe((int32_t)nused, b, 1);
+          nused &= ~(1u << b);
+          // Rule 5: a bin at least half full (load >= cap/2, i.e. 2 room <=
+          // cap) divides once, adding an empty bin of its type at the next
+          // free slot.  Without a division that slot is rewritten with the
+          // empty word it already holds (room 0, type 0), which no scan picks.
+          const bool split = ((nodiv >> b) & 1u) && 2 * room <= cap;
+          nodiv &= split ? ~(1u << b) : 0xFFFFFFFFu;
           const int nbn = nb;
           nb += split ? 1 : 0;
-          const int swn = slot_word(nbn, stride);
           const int32_t capn = split ? cap : 0;
-          myA[swn] = (capn << 10) | (nbn << 5) | (split ? type : 0);
+          *slot_at(myA, nbn, step) = (capn << 10) | (nbn << 5) | (split ? type : 0);
           locs |= (uint32_t)b << (5 * d);
         }
+        used = ~nused;
         key = ((uint32_t)cost << 10) | (uint32_t)r;
       }
       // group minimum of (cost, rank): lowest rank on ties
@@ -752,9 +765,8 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           a.assign[off + s_ci[lq + lane]] = before + (int)__popc(wused & ((1u << b) - 1u));
         }
         if (lane < 32 && ((wused >> lane) & 1u)) {
-          const int32_t* winA = arrA + 4 * (g * group + wr);
           a.types[off + before + (int)__popc(wused & ((1u << lane) - 1u))] =
-              winA[slot_word(lane, stride)] & 31;
+              *slot_at(arrA + 4 * (g * group + wr), lane, step) & 31;
         }
       }
     }
