@@ -395,7 +395,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     // decision state (extended runs only)
     int fd = -1, ft1 = -1, ft2 = -1, nev = 0;
     int64_t placed = 0;
-    int32_t thr[5] = {0, 0, 0, 0, 0};
+    // lanes 0..4 and 8..12 hold the bucket thresholds 1..5, the others never pass
+    int32_t thr_lane = 0x7FFFFFFF;
     float xcap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float inv_cap_lane = 0.0f;
     if constexpr (EXT) {
@@ -406,8 +407,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       }
       // room r is in bucket floor(6r/(B_1+1)) = number of k in 1..5 with
       // r >= ceil(k(B_1+1)/6)
-#pragma unroll
-      for (int k = 1; k <= 5; ++k) thr[k - 1] = (int32_t)(((int64_t)k * (B1 + 1) + 5) / 6);
+      if ((lane & 7) < 5 && lane < 16)
+        thr_lane = (int32_t)(((int64_t)((lane & 7) + 1) * (B1 + 1) + 5) / 6);
       if (lane < 8) hist[lane] = 0;
       // features that are constants of the instance: B_2..B_5 over B_1, and
       // lane k's 1/B_k for the fill of the smallest fitting type
@@ -417,12 +418,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         xcap[k - 1] = k < n ? (float)readlane(cap_lane, k) * inv_b1 : 0.0f;
       inv_cap_lane = lane < n ? 1.0f / (float)cap_lane : 0.0f;
     }
-    // rooms and capacities are int32
-    auto bucket = [&](int32_t r) -> int {
-      int b = 0;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b += r >= thr[k] ? 1 : 0;
-      return b;
+    // rooms and capacities are int32.  The buckets of r0 (lanes 0..4) and r1
+    // (lanes 8..12) in one ballot: bits 0..4 and 8..12 of it.
+    auto buckets = [&](int32_t r0, int32_t r1) -> uint64_t {
+      return ballot((lane < 8 ? r0 : r1) >= thr_lane);
     };
 
     int nlive = 0, nb = 0, dead = 0;
@@ -534,11 +533,11 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           const K rnew = room_of<CRIT>(nk);
           if (rnew < (K)T) ++dead;
           if constexpr (EXT) {
-            const int b0 = bucket((int32_t)rnew + w), b1 = bucket((int32_t)rnew);
-            if (b0 != b1 && lane == 0) {
-              atomicAdd(&hist[b0], -1);
-              atomicAdd(&hist[b1], 1);
-            }
+            // the bin moves from the bucket of its old room to that of its
+            // new one: lane 0 takes it out, lane 1 puts it in
+            const uint64_t ge = buckets((int32_t)rnew + w, (int32_t)rnew);
+            const int b0 = (int)__popcll(ge & 0x1Full), b1 = (int)__popcll(ge & 0x1F00ull);
+            if (b0 != b1 && lane < 2) atomicAdd(&hist[lane == 0 ? b0 : b1], lane == 0 ? -1 : 1);
           }
         } else {
           // nothing fits: open a bin of the chosen type
@@ -661,7 +660,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           cost += Bt;
           if (room < (K)T) ++dead;
           if constexpr (EXT) {
-            if (lane == 0) atomicAdd(&hist[bucket((int32_t)room)], 1);
+            const int bn = (int)__popcll(buckets((int32_t)room, (int32_t)room) & 0x1Full);
+            if (lane == 0) hist[bn] += 1;
           }
         }
         if constexpr (EXT) placed += w;
