@@ -526,9 +526,12 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 // ---------------------------------------------------------------------------
 // Second heuristic with 32-bit bin words (B_1 <= 32767), the common case.
 //
-// Bin b of thread t is one word of the workgroup's LDS array A, at
-// (b >> 2) * 4*blockDim + 4*t + (b & 3), with the bin's type k < 32:
+// Bin b of lane l of wavefront v is one word of the workgroup's LDS array A,
+// at (v * nbslots + b) * 64 + l, with the bin's type k < 32:
 //   A = room << 10 | b << 5 | k.
+// Slot b of a lane is 64 words (256 bytes) past its slot 0, so its address
+// is one shift-add, two slots are one ds_read2st64, and every lane of a wave
+// reads and writes its own bank whatever slot it addresses.
 // The candidate key of weight w in bin b (W10 = w << 10, R = 32767):
 //   BF: A - W10                  least room after, then lowest b; a bin the
 //                                item does not fit wraps to >= 2^31
@@ -555,12 +558,8 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 // ---------------------------------------------------------------------------
 constexpr int32_t kR5 = 32767;
 
-// slot b of the packer whose slot 0 is `first`: (b >> 2) * stride + (b & 3)
-// words on, i.e. b + (b >> 2) * step words with step = stride - 4
-// (< 2^24 for the largest workgroup)
-__device__ __forceinline__ int32_t* slot_at(int32_t* first, int b, unsigned step) {
-  return first + (int)(__umul24((unsigned)(b >> 2), step) + (unsigned)b);
-}
+// slot b of the packer whose slot 0 is `first`
+__device__ __forceinline__ int32_t* slot_at(int32_t* first, int b) { return first + 64 * b; }
 
 __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int group) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -570,8 +569,6 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   __shared__ int s_slot;
   const int tid = threadIdx.x, B = blockDim.x;
   const int spr = B / group;  // subsets per round
-  const int stride = 4 * B;
-  const unsigned step = (unsigned)stride - 4u;
   int32_t* arrA = reinterpret_cast<int32_t*>(smem);
   int32_t* tmplA = arrA + (size_t)nbslots * B;  // [nbslots]
   int32_t* s_ci = tmplA + nbslots;              // [B] chunk items
@@ -579,7 +576,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   int32_t* s_ct = s_cw + B;                     // [B] type << 16 | capacity of a new bin
   int32_t* s_u = s_ct + B;                      // [spr] used bins
   int32_t* s_cst = s_u + spr;                   // [spr] subset cost
-  int32_t* myA = arrA + 4 * tid;
+  int32_t* myA = arrA + ((tid >> 6) * nbslots) * 64 + (tid & 63);
   const int g = tid / group, r = tid - g * group;
   const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
 
@@ -653,8 +650,14 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       if (active) {
         // bins not used yet and bins not divided yet, one bit per slot
         uint32_t nused = 0xFFFFFFFFu, nodiv = 0xFFFFFFFFu;
-        for (int gi = 0; gi < (nbslots >> 2); ++gi)
-          *reinterpret_cast<int4*>(myA + gi * stride) = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
+        for (int gi = 0; gi < (nbslots >> 2); ++gi) {
+          const int4 tv = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
+          int32_t* const p = myA + 256 * gi;
+          p[0] = tv.x;
+          p[64] = tv.y;
+          p[128] = tv.z;
+          p[192] = tv.w;
+        }
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
         uint32_t cu = digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
         int nb = n;
@@ -677,8 +680,9 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           uint32_t best = 0xFFFFFFFFu;
           int gi = 0;
           for (; gi + 1 < ng; gi += 2) {
-            const uint4 v = *reinterpret_cast<const uint4*>(myA + gi * stride);
-            const uint4 u = *reinterpret_cast<const uint4*>(myA + (gi + 1) * stride);
+            const uint32_t* const pg = reinterpret_cast<const uint32_t*>(myA + 256 * gi);
+            const uint4 v = make_uint4(pg[0], pg[64], pg[128], pg[192]);
+            const uint4 u = make_uint4(pg[256], pg[320], pg[384], pg[448]);
             const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
             const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
             const uint32_t k4 = ((u.x ^ sx) + x) & msk, k5 = ((u.y ^ sx) + x) & msk;
@@ -690,7 +694,8 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
             best = min(min(best, k6), k7);
           }
           if (gi < ng) {
-            const uint4 v = *reinterpret_cast<const uint4*>(myA + gi * stride);
+            const uint32_t* const pg = reinterpret_cast<const uint32_t*>(myA + 256 * gi);
+            const uint4 v = make_uint4(pg[0], pg[64], pg[128], pg[192]);
             const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
             const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
             best = min(min(best, k0), k1);
@@ -703,7 +708,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const bool found = best < (1u << 25);
           const int b = found ? (int)((best >> 5) & 31u) : nb;
           const int type = found ? (int)(best & 31u) : (tc >> 16);
-          int32_t* const pb = slot_at(myA, b, step);
+          int32_t* const pb = slot_at(myA, b);
           const int32_t word = *pb;  // a free slot holds an empty bin word
           const int32_t cap = s_caps[type];
           const int32_t room = (found ? (word >> 10) : cap) - w;
@@ -722,7 +727,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           const int nbn = nb;
           nb += split ? 1 : 0;
           const int32_t capn = split ? cap : 0;
-          *slot_at(myA, nbn, step) = (capn << 10) | (nbn << 5) | (split ? type : 0);
+          *slot_at(myA, nbn) = (capn << 10) | (nbn << 5) | (split ? type : 0);
           locs |= (uint32_t)b << (5 * d);
         }
         used = ~nused;
@@ -766,7 +771,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
         }
         if (lane < 32 && ((wused >> lane) & 1u)) {
           a.types[off + before + (int)__popc(wused & ((1u << lane) - 1u))] =
-              *slot_at(arrA + 4 * (g * group + wr), lane, step) & 31;
+              *slot_at(arrA + ((g * wpg + (wr >> 6)) * nbslots) * 64 + (wr & 63), lane) & 31;
         }
       }
     }

@@ -91,6 +91,38 @@ def test_heuristic_options(V, orc, h, kw):
     assert_batch_equal(b, db, oracle_batch(b, h, **kw))
 
 
+@pytest.mark.parametrize("kw", [{}, {"force_crit": 0}, {"force_crit": 1}, {"force_crit": 2},
+                                {"s2": 6}, {"type_rule": 1}])
+def test_h2_one_word_bins_at_their_limit(V, orc, kw):
+    """B_1 = 32767, the largest capacity of the one-word bin encoding: rooms
+    and weights up to 32767 reach the ends of every key's range (the Worst
+    Fit key among them), 16 types fill 5-bit type fields, and runs of equal
+    weights make the lowest-slot tie rule decide."""
+    rng = np.random.default_rng(450)
+    ws, cs = [], []
+    for i in range(48):
+        n = 16 if i % 2 == 0 else int(rng.integers(1, 16))
+        tail = np.sort(rng.choice(np.arange(1, 32767), size=n - 1, replace=False))[::-1]
+        caps = np.concatenate([[32767], tail]).astype(np.int32)
+        m = int(rng.integers(1, 240))
+        kind = i % 4
+        if kind == 0:    # anywhere in [1, 32767]
+            w = rng.integers(1, 32768, size=m)
+        elif kind == 1:  # heavy: every item near the largest capacity
+            w = rng.integers(32000, 32768, size=m)
+        elif kind == 2:  # few distinct weights: ties of equal rooms
+            w = rng.choice([1, 8191, 10922, 16383, 16384, 32767], size=m)
+        else:            # light items: many placements into the same bins
+            w = rng.integers(1, 64, size=m)
+        ws.append(w.astype(np.int32))
+        cs.append(caps)
+    seeds = rng.integers(0, 2**63, size=len(ws), dtype=np.int64).astype(np.uint64)
+    b = inputs.make_batch(ws, cs, None, seeds)
+    db = run_batch(V, b, "H2", **kw)
+    assert db.max_cap == 32767
+    assert_batch_equal(b, db, oracle_batch(b, "H2", **kw))
+
+
 @pytest.mark.parametrize("h", HEUR)
 def test_wide_capacities(V, orc, h):
     """Capacities above 32767 take the 64-bit key path."""
