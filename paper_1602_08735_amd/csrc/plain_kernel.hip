@@ -52,6 +52,15 @@ __device__ __forceinline__ int kidx(int p) {
   return (p & ~255) + ((p & 63) << 2) + ((p >> 6) & 3);
 }
 
+// One key written by the lane that holds it.  Position p belongs to lane
+// p & 63, and relative to that lane's first key (keys + 4 * lane, `mine`) it
+// sits (p & ~255) + ((p >> 6) & 3) entries on: an offset the whole wavefront
+// shares, so the address is the lane's own base plus a scalar.
+template <typename K>
+__device__ __forceinline__ void put_key(K* mine, int lane, int p, K v) {
+  if (lane == (p & 63)) mine[(p & ~255) + ((p >> 6) & 3)] = v;
+}
+
 template <typename K>
 __device__ __forceinline__ void load_group(const K* keys, int g, int lane, K (&k)[4]) {
   if constexpr (sizeof(K) == 4) {
@@ -336,6 +345,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     if (slot >= a.num) break;
     const int inst = a.sched ? uniform(a.sched[slot]) : slot;
     if constexpr (SPILL) carve(a.spill + (size_t)inst * (size_t)per_wave);
+    K* const mine = keys + 4 * lane;
     // inputs come from instance `src_i` (entries may share an instance)
     const int src_i = (EXT && a.src) ? uniform(a.src[inst]) : inst;
     const int64_t off = a.item_off[src_i];
@@ -528,7 +538,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         }
         if (p >= 0) {
           // Rule 4: place into the chosen open bin
-          if (lane == (p & 63)) keys[kidx(p)] = nk;
+          put_key(mine, lane, p, nk);
           if (dsl && lane == 0) bload[pid[p]] += w;
           const K rnew = room_of<CRIT>(nk);
           if (rnew < (K)T) ++dead;
@@ -568,12 +578,12 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             }
             if (open >= a.active_limit) {
               const int pf = (int)(wave_min(best) & KT::POS);
-              if (lane == (pf & 63))
-                keys[kidx(pf)] = CRIT == WF ? ((KT::R << KT::SH) | (K)pf) : (K)pf;
+              put_key(mine, lane, pf, CRIT == WF ? ((KT::R << KT::SH) | (K)pf) : (K)pf);
               ++dead;
             }
           }
-          const uint64_t fm = ballot(lane < n && cap_lane >= w);
+          // types holding the item (lanes >= n hold capacity 0 and w >= 1)
+          const uint64_t fm = ballot(cap_lane >= w);
           const int smallest = (int)__popcll(fm) - 1;
           int t = a.type_rule == 1 ? 0 : smallest;
           if constexpr (EXT) {
@@ -651,7 +661,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           if ((p & 255) == 0) fill_group(keys, p >> 8, lane, empty_key<CRIT, K>());
           const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)p)
                                    : ((room << KT::SH) | (K)p);
-          if (lane == (p & 63)) keys[kidx(p)] = key;
+          put_key(mine, lane, p, key);
           if (lane == 0) pid[p] = (Pid)id;
           if (dsl && lane == 0) bload[id] = w;
           const bool out_types = !EXT || !a.src;
