@@ -434,9 +434,15 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       return ballot((lane < 8 ? r0 : r1) >= thr_lane);
     };
 
-    int nlive = 0, nb = 0, dead = 0;
+    int nlive = 0, nb = 0;
+    // least room written since the last compaction (a closed bin counts as
+    // room 0): some bin is dead at the next chunk iff it is below that
+    // chunk's bound, or the bound has risen anyway
+    uint32_t minroom = 0xFFFFFFFFu;
     int32_t tprev = 0;
-    int64_t cost = 0;
+    // with 32-bit keys m <= 65535 and B_1 <= 32767, so the cost fits int32
+    using Cost = typename std::conditional<sizeof(K) == 4, int32_t, int64_t>::type;
+    Cost cost = 0;
     int32_t typebuf = 0;
     // First Fit: upper bound on the room of every bin in the scan array; an
     // item heavier than it fits nowhere, so its scan is skipped (rooms only
@@ -445,9 +451,9 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     int64_t ub = 0;
     for (int c = 0; c < nch; ++c) {
       const int32_t T = uniform(smin[c]);
-      if (nlive > 0 && (dead > 0 || T > tprev)) {
+      if (nlive > 0 && (minroom < (uint32_t)T || T > tprev)) {
         nlive = uniform(compact<CRIT, K>(keys, pid, nlive, T, lane));
-        dead = 0;
+        minroom = 0xFFFFFFFFu;
       }
       tprev = T;
       const int q = (c << 6) + lane;
@@ -541,7 +547,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           put_key(mine, lane, p, nk);
           if (dsl && lane == 0) bload[pid[p]] += w;
           const K rnew = room_of<CRIT>(nk);
-          if (rnew < (K)T) ++dead;
+          minroom = min(minroom, (uint32_t)rnew);
           if constexpr (EXT) {
             // the bin moves from the bucket of its old room to that of its
             // new one: lane 0 takes it out, lane 1 puts it in
@@ -579,7 +585,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             if (open >= a.active_limit) {
               const int pf = (int)(wave_min(best) & KT::POS);
               put_key(mine, lane, pf, CRIT == WF ? ((KT::R << KT::SH) | (K)pf) : (K)pf);
-              ++dead;
+              minroom = 0;
             }
           }
           // types holding the item (lanes >= n hold capacity 0 and w >= 1)
@@ -661,14 +667,18 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           if ((p & 255) == 0) fill_group(keys, p >> 8, lane, empty_key<CRIT, K>());
           const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)p)
                                    : ((room << KT::SH) | (K)p);
-          put_key(mine, lane, p, key);
-          if (lane == 0) pid[p] = (Pid)id;
+          // the lane that holds position p also writes its id (pid + lane is
+          // that lane's base in the position -> id map)
+          if (lane == (p & 63)) {
+            mine[(p & ~255) + ((p >> 6) & 3)] = key;
+            pid[(p & ~63) + lane] = (Pid)id;
+          }
           if (dsl && lane == 0) bload[id] = w;
           const bool out_types = !EXT || !a.src;
           typebuf = lane == (id & 63) ? t : typebuf;
           if (out_types && (id & 63) == 63) a.types[off + (id - 63) + lane] = typebuf;
           cost += Bt;
-          if (room < (K)T) ++dead;
+          minroom = min(minroom, (uint32_t)room);
           if constexpr (EXT) {
             const int bn = (int)__popcll(buckets((int32_t)room, (int32_t)room) & 0x1Full);
             if (lane == 0) hist[bn] += 1;
@@ -681,6 +691,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     }
     if ((!EXT || !a.src) && (nb & 63) && lane < (nb & 63))
       a.types[off + (nb & ~63) + lane] = typebuf;
+    int64_t out_cost = cost;
     if (dsl) {
       // downsized cost: every bin at the smallest capacity holding its load
       int64_t ds = 0;
@@ -693,11 +704,11 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         }
         ds += c;
       }
-      cost = wave_sum64(ds);
+      out_cost = wave_sum64(ds);
     }
     if (lane == 0) {
       a.nbins[inst] = nb;
-      a.cost[inst] = cost;
+      a.cost[inst] = out_cost;
     }
   }
 }
