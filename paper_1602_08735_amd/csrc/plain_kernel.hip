@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     // item heavier than it fits nowhere, so its scan is skipped (rooms only
     // shrink, a new bin raises the bound, and a scan that finds no fit sets it
     // to the largest room exactly)
-    int64_t ub = 0;
+    int32_t ub = 0;  // rooms are int32 with either key width
     for (int c = 0; c < nch; ++c) {
       const int32_t T = uniform(smin[c]);
       if (nlive > 0 && (minroom < (uint32_t)T || T > tprev)) {
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         const K wk = (K)w << KT::SH;
         int p = -1;
         K nk = 0;
-        const int ng = (CRIT == FF && (int64_t)w > ub) ? 0 : uniform((nlive + 255) >> 8);
+        const int ng = (CRIT == FF && w > ub) ? 0 : uniform((nlive + 255) >> 8);
         if constexpr (CRIT == FF) {
           // the lowest position among the bins the item fits: a key with its
           // halves swapped is pos << SH | room, so the least of those over
@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
               p = (int)(best >> KT::SH);
               nk = (((best & KT::POS) << KT::SH) | (K)p) - wk;
             } else {
-            if (ng > 0) ub = (int64_t)(~wave_min(~kmax) >> KT::SH);
+            if (ng > 0) ub = (int32_t)(~wave_min(~kmax) >> KT::SH);
             }
           }
         } else {
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           }
           const int32_t Bt = readlane(cap_lane, t);
           const K room = (K)(Bt - w);
-          if constexpr (CRIT == FF) ub = max(ub, (int64_t)room);
+          if constexpr (CRIT == FF) ub = max(ub, (int32_t)room);
           p = nlive;
           nlive = uniform(nlive + 1);
           const int id = nb;
