@@ -404,7 +404,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     }
     // decision state (extended runs only)
     int fd = -1, ft1 = -1, ft2 = -1, nev = 0;
-    int64_t placed = 0;
+    // weight placed so far: int32 with 32-bit keys (m <= 65535, B_1 <= 32767)
+    typename std::conditional<sizeof(K) == 4, int32_t, int64_t>::type placed = 0;
     // lanes 0..4 and 8..12 hold the bucket thresholds 1..5, the others never pass
     int32_t thr_lane = 0x7FFFFFFF;
     float xcap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -600,7 +601,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
               // decision features (wave-uniform values)
               const int qq = (c << 6) + jj;
               const int rem = m - qq - 1;
-              const int64_t rsum = total - placed - w;
+              const int64_t rsum = total - (int64_t)placed - w;
               int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
               after = min(after, next_min);
               const float inv_b1 = 1.0f / (float)B1;
