@@ -564,6 +564,9 @@ __device__ __forceinline__ int32_t* slot_at(int32_t* first, int b) { return firs
 __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int group) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ __align__(16) int32_t s_caps[kMaxTypes];
+  // per criterion c, the constants of its key ((A ^ s) + x) & mask with
+  // x = (W10 ^ nm) + ad: {s, nm, ad, mask}, one 16-byte read per placement
+  __shared__ __align__(16) uint32_t s_keyc[4 * 3];
   __shared__ uint32_t s_wmin[16];
   __shared__ int s_flag;
   __shared__ int s_slot;
@@ -579,6 +582,16 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   int32_t* myA = arrA + ((tid >> 6) * nbslots) * 64 + (tid & 63);
   const int g = tid / group, r = tid - g * group;
   const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
+  if (tid < 12) {
+    const int c = tid >> 2, f = tid & 3;
+    const bool wf = c == WF;
+    const uint32_t v = f == 0   ? (wf ? 0xFFFFFC00u : 0u)
+                       : f == 1 ? (wf ? 0u : 0xFFFFFFFFu)
+                       : f == 2 ? (wf ? (uint32_t)(kR5 - 0x3FFFFF) << 10 : 1u)
+                                : (c == FF ? 0x800003FFu : 0xFFFFFFFFu);
+    s_keyc[tid] = v;
+  }
+  __syncthreads();
 
   int cursor = blockIdx.x;
   for (;;) {
@@ -659,21 +672,28 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           p[192] = tv.w;
         }
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
-        uint32_t cu = digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
+        // A forced criterion c runs the same digit iteration from a word
+        // whose every digit is c: 0, 2^31 (3 * 2^31 = 2^32 + 2^31) and
+        // 2^32 - 1 (its deficit from 2^32 triples per step and stays below
+        // 3^6 over at most six placements).
+        uint32_t cu = a.force_crit >= 0
+                          ? (a.force_crit == 0 ? 0u : (a.force_crit == 1 ? 0x80000000u : 0xFFFFFFFFu))
+                          : digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
         int nb = n;
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
           const int32_t w = s_cw[lq + d];
           const int32_t tc = s_ct[lq + d];
-          const int drawn = digits_next(cu);
-          const int crit = a.force_crit >= 0 ? a.force_crit : drawn;
-          // x = XW or -W10, as (W10 ^ nm) + ad without a branch
-          const bool wf = crit == WF;
-          const uint32_t sx = wf ? 0xFFFFFC00u : 0u;
-          const uint32_t nm = wf ? 0u : 0xFFFFFFFFu;
-          const uint32_t ad = wf ? (uint32_t)(kR5 - 0x3FFFFF) << 10 : 1u;
-          const uint32_t x = (((uint32_t)w << 10) ^ nm) + ad;
-          const uint32_t msk = crit == FF ? 0x800003FFu : 0xFFFFFFFFu;
+          // the criterion digit floor(3u / 2^32) times 16, the byte offset of
+          // its key constants: floor(48u / 2^32) with the low four bits cleared
+          const uint32_t koff = __umulhi(cu, 48u) & 0x30u;
+          cu *= 3u;
+          // x = XW or -W10, as (W10 ^ nm) + ad
+          const uint4 kc = *reinterpret_cast<const uint4*>(
+              reinterpret_cast<const unsigned char*>(s_keyc) + koff);
+          const uint32_t sx = kc.x;
+          const uint32_t x = (((uint32_t)w << 10) ^ kc.y) + kc.z;
+          const uint32_t msk = kc.w;
           // groups that can hold bins after t placements (each adds <= 2)
           const int ng = (min(nbslots, n + 2 * t) + 3) >> 2;
           // two groups per LDS round trip, then an odd last group alone

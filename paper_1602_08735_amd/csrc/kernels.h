@@ -88,8 +88,9 @@ inline bool plain_ext(const BatchArgs& a) {
   return a.src || a.force || a.feat_out || a.info_out || a.type_rule == 2;
 }
 size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide);
-// H2 kernels: two 32-bit words per bin (the fast form), one packed 32-bit
-// word per bin (when the fast form's LDS does not fit), 64-bit bins (wide)
+// H2 kernels: one 32-bit key word per bin with a chunk of resolved positions
+// (the fast form), one packed 32-bit word per bin (when the fast form's LDS
+// does not fit), 64-bit bins (wide)
 enum class H2Kernel { kSlim, kPacked, kWide };
 size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k);
 int h2_group(int s2);
