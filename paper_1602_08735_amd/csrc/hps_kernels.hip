@@ -567,6 +567,9 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   // per criterion c, the constants of its key ((A ^ s) + x) & mask with
   // x = (W10 ^ nm) + ad: {s, nm, ad, mask}, one 16-byte read per placement
   __shared__ __align__(16) uint32_t s_keyc[4 * 3];
+  // per bin type k: {B_k, the word of an empty bin of type k in slot 0
+  // (B_k << 10 | k), floor(B_k / 2), 0}
+  __shared__ __align__(16) int4 s_type[kMaxTypes];
   __shared__ uint32_t s_wmin[16];
   __shared__ int s_flag;
   __shared__ int s_slot;
@@ -576,7 +579,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
   int32_t* tmplA = arrA + (size_t)nbslots * B;  // [nbslots]
   int32_t* s_ci = tmplA + nbslots;              // [B] chunk items
   int32_t* s_cw = s_ci + B;                     // [B] chunk weights
-  int32_t* s_ct = s_cw + B;                     // [B] type << 16 | capacity of a new bin
+  int32_t* s_ct = s_cw + B;                     // [B] type of a new bin
   int32_t* s_u = s_ct + B;                      // [spr] used bins
   int32_t* s_cst = s_u + spr;                   // [spr] subset cost
   int32_t* myA = arrA + ((tid >> 6) * nbslots) * 64 + (tid & 63);
@@ -618,6 +621,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
       const int32_t room = tid < n ? s_caps[tid] : 0;
       tmplA[tid] = (room << 10) | (tid << 5) | (tid < n ? tid : 0);
     }
+    if (tid < n) s_type[tid] = make_int4(s_caps[tid], (s_caps[tid] << 10) | tid, s_caps[tid] >> 1, 0);
     const uint64_t seed = inst_seed(a, inst);
     Rule1Perm perm;
     perm.init(seed, (uint32_t)m);
@@ -647,7 +651,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           int t = 0;
           if (a.type_rule != 1)
             for (int kk = 1; kk < n; ++kk) t += s_caps[kk] >= w ? 1 : 0;
-          s_ct[tid] = (t << 16) | s_caps[t];
+          s_ct[tid] = t;
         }
         __syncthreads();
       }
@@ -683,7 +687,7 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
           const int32_t w = s_cw[lq + d];
-          const int32_t tc = s_ct[lq + d];
+          const int32_t tn = s_ct[lq + d];
           // the criterion digit floor(3u / 2^32) times 16, the byte offset of
           // its key constants: floor(48u / 2^32) with the low four bits cleared
           const uint32_t koff = __umulhi(cu, 48u) & 0x30u;
@@ -727,27 +731,30 @@ __global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int grou
           // branches, and selects cost less than both branch bodies.
           const bool found = best < (1u << 25);
           const int b = found ? (int)((best >> 5) & 31u) : nb;
-          const int type = found ? (int)(best & 31u) : (tc >> 16);
+          const int type = found ? (int)(best & 31u) : tn;
           int32_t* const pb = slot_at(myA, b);
           const int32_t word = *pb;  // a free slot holds an empty bin word
-          const int32_t cap = s_caps[type];
-          const int32_t room = (found ? (word >> 10) : cap) - w;
+          const int4 ty = s_type[type];
+          // the bin's word after the item: the chosen bin's, or an empty bin
+          // of the item's type in slot b, with the room lowered by w (it
+          // fits, so the low fields are untouched)
+          const int32_t nw = (found ? word : (ty.y | (b << 5))) - (w << 10);
+          *pb = nw;
           nb += found ? 0 : 1;
-          *pb = (room << 10) | (b << 5) | type;
           // a bin's first item adds its capacity to the cost (bit b of nused
           // sign-extended: all ones or zero)
-          cost += cap & __builtin_amdgcn_sbfe((int32_t)nused, b, 1);
+          cost += ty.x & __builtin_amdgcn_sbfe((int32_t)nused, b, 1);
           nused &= ~(1u << b);
-          // Rule 5: a bin at least half full (load >= cap/2, i.e. 2 room <=
-          // cap) divides once, adding an empty bin of its type at the next
-          // free slot.  Without a division that slot is rewritten with the
-          // empty word it already holds (room 0, type 0), which no scan picks.
-          const bool split = ((nodiv >> b) & 1u) && 2 * room <= cap;
+          // Rule 5: a bin at least half full (2 room <= cap, i.e. room <=
+          // floor(cap / 2)) divides once, adding an empty bin of its type at
+          // the next free slot.  Without a division that slot is rewritten
+          // with the empty word it already holds (room 0, type 0), which no
+          // scan picks.
+          const bool split = ((nodiv >> b) & 1u) && (nw >> 10) <= ty.z;
           nodiv &= split ? ~(1u << b) : 0xFFFFFFFFu;
           const int nbn = nb;
           nb += split ? 1 : 0;
-          const int32_t capn = split ? cap : 0;
-          *slot_at(myA, nbn) = (capn << 10) | (nbn << 5) | (split ? type : 0);
+          *slot_at(myA, nbn) = (split ? ty.y : 0) | (nbn << 5);
           locs |= (uint32_t)b << (5 * d);
         }
         used = ~nused;
