@@ -56,8 +56,8 @@ ALU_PEAK = 256 * 4 * 16 * 2.4e9   # VALU lane-ops/s: CUs x SIMDs x lanes x clock
 # (x1) -- profiles/pack_kernels_uniform_batch.md.  Taken again whenever a
 # kernel changes (a launch without a current figure reports null).
 MEASURED_HBM_BYTES = {"H2": 48.14e6, "FF": 50.36e6, "BF": 50.48e6, "WF": 51.20e6,
-                      "H1": 47.23e6, "FF+scorer": 48.28e6, "BF+scorer": 48.39e6,
-                      "WF+scorer": 49.25e6}
+                      "H1": 47.23e6, "FF+scorer": None, "BF+scorer": None,
+                      "WF+scorer": None}
 
 
 # Exact solver leg (outside the step): instances of the uniform distribution

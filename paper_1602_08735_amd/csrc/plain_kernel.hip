@@ -597,7 +597,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             const int d = nev;
             nev = uniform(nev + 1);
             const bool dump = d == fd && (a.feat_out || a.info_out);
-            if (a.type_rule == 2 || dump) {
+            // features only where the scorer has a choice (or a dump asks)
+            if ((a.type_rule == 2 && smallest > 0) || dump) {
               // decision features (wave-uniform values)
               const int qq = (c << 6) + jj;
               const int rem = m - qq - 1;
