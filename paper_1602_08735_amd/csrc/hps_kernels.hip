@@ -561,7 +561,9 @@ constexpr int32_t kR5 = 32767;
 // slot b of the packer whose slot 0 is `first`
 __device__ __forceinline__ int32_t* slot_at(int32_t* first, int b) { return first + 64 * b; }
 
-__global__ void __launch_bounds__(1024) k_h2s(BatchArgs a, int nbslots, int group) {
+// At most 64 VGPRs: eight wavefronts per SIMD instead of seven at 65.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+k_h2s(BatchArgs a, int nbslots, int group) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ __align__(16) int32_t s_caps[kMaxTypes];
   // per criterion c, the constants of its key ((A ^ s) + x) & mask with
