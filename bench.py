@@ -55,9 +55,9 @@ ALU_PEAK = 256 * 4 * 16 * 2.4e9   # VALU lane-ops/s: CUs x SIMDs x lanes x clock
 # FETCH_SIZE (x2: it counts half of a known-size copy's reads) and WRITE_SIZE
 # (x1) -- profiles/pack_kernels_uniform_batch.md.  Taken again whenever a
 # kernel changes (a launch without a current figure reports null).
-MEASURED_HBM_BYTES = {"H2": None, "FF": 50.35e6, "BF": 50.37e6, "WF": 51.11e6,
-                      "H1": 47.23e6, "FF+scorer": 48.42e6, "BF+scorer": 48.29e6,
-                      "WF+scorer": 49.36e6}
+MEASURED_HBM_BYTES = {"H2": 58.75e6, "FF": 50.60e6, "BF": 50.34e6, "WF": 49.18e6,
+                      "H1": 47.21e6, "FF+scorer": 46.48e6, "BF+scorer": 46.29e6,
+                      "WF+scorer": 49.45e6}
 
 
 # Exact solver leg (outside the step): instances of the uniform distribution
