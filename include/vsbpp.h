@@ -37,10 +37,13 @@
  *     4-round balanced Feistel network whose round function is SplitMix64,
  *     restricted to [0,m) by cycle walking; position q holds item pi(q) and
  *     sublists/subsets are consecutive runs of positions;
- *   - Rule 3 draws criterion floor(3*hi32(x)/2^32) from the SplitMix64 output
- *     x for counter q (H1, position q) or (I*S! + r)*S + t (H2, subset I,
- *     permutation rank r, placement t), with per-purpose keys derived from
- *     the seed;
+ *   - Rule 3's equal-probability draw uses SplitMix64 (Steele, Lea & Flood,
+ *     2014) with one key per purpose derived from the seed.  H1: position q
+ *     takes the output x for counter q and criterion floor(3*hi32(x)/2^32).
+ *     H2: the packing of permutation rank r of subset I (S items) takes one
+ *     output for counter I*S! + r; with h its high 32 bits, placement t
+ *     (0-based) takes base-3 digit t+1 of h/2^32, i.e.
+ *     floor(3^(t+1)*h/2^32) mod 3;
  *   - Rule 5 is checked right after every placement, at most once per bin;
  *   - output bin ids: bins holding items, in creation order, packer after
  *     packer (sublist or subset order); empty Rule-2/Rule-5 bins cost nothing
@@ -77,8 +80,13 @@ enum {
   VSBPP_E_HEURISTIC = -5, /* unknown heuristic                                */
   VSBPP_E_OPTION = -6,    /* bad option (s1, s2, type rule, criterion, order) */
   VSBPP_E_DEVICE = -7,    /* no usable gfx950 device or a HIP runtime error   */
-  VSBPP_E_NOMEM = -8      /* device allocation failed                          */
+  VSBPP_E_NOMEM = -8,     /* device allocation failed                          */
+  VSBPP_E_MODEL = -9      /* the learned type rule without a model, or a model
+                             file that is missing, of the wrong size, with
+                             n_out outside 1..16 or a non-finite parameter    */
 };
+/* Argument checks run in this order and the first failure is returned:
+ * NULL, SIZE, CAPS, WEIGHT, HEURISTIC, OPTION, MODEL. */
 
 /* Options.  Fill with vsbpp_options_init() first. */
 typedef struct vsbpp_options {
@@ -239,8 +247,9 @@ typedef struct vsbpp_plan vsbpp_plan;
 int32_t vsbpp_plan_create(const vsbpp_batch* batch, int32_t heuristic, const vsbpp_options* opt,
                           const vsbpp_launch* launch, uint32_t flags, vsbpp_plan** out);
 /* As vsbpp_plan_create with a scorer: opt->type_rule VSBPP_TYPE_LEARNED and
- * d_model (a device pointer to a vsbpp_model, which must stay valid while
- * the plan is used); plain FF/BF/WF only.  Declared with the scorer below. */
+ * d_model (a device pointer to a vsbpp_model, e.g. from vsbpp_model_load,
+ * which must stay valid while the plan is used; VSBPP_E_MODEL when it is
+ * NULL); plain FF/BF/WF only.  Declared with the scorer below. */
 struct vsbpp_model;
 int32_t vsbpp_plan_create_ex(const vsbpp_batch* batch, int32_t heuristic,
                              const vsbpp_options* opt, const struct vsbpp_model* d_model,
@@ -255,7 +264,7 @@ void vsbpp_plan_destroy(vsbpp_plan* plan);
 /* Exact optimum of every instance of a device-resident batch with at most
  * 12 items per instance (batch->max_items <= 12), for measuring heuristic
  * and learned packings against the optimum.  The cost of a packing is the
- * sum of the capacities of its bins (Section 2), so a bin holding a set of
+ * sum of the capacities of its bins (Section 1, formal definition), so a bin holding a set of
  * items costs the smallest capacity that holds their total and the optimum
  * is the cheapest partition of the items into such sets.  The call evaluates
  * it exactly, by dynamic programming over the subsets of the items.
@@ -346,7 +355,8 @@ typedef struct vsbpp_decisions {
 } vsbpp_decisions;
 
 /* vsbpp_pack_batch with a scorer (d_model: device pointer to a vsbpp_model,
- * required when opt->type_rule is VSBPP_TYPE_LEARNED, else ignored) and
+ * e.g. from vsbpp_model_load, required when opt->type_rule is
+ * VSBPP_TYPE_LEARNED -- VSBPP_E_MODEL when it is NULL -- else ignored) and
  * decision hooks (dec may be NULL).  Plain FF/BF/WF only when either is
  * used.  Asynchronous on hip_stream, no allocation. */
 int32_t vsbpp_pack_batch_ex(const vsbpp_batch* batch, int32_t heuristic,
@@ -406,6 +416,41 @@ void vsbpp_trainer_destroy(vsbpp_trainer* tr);
 int32_t vsbpp_lower_bounds(int32_t num, const int32_t* d_weights, const int64_t* d_item_off,
                            const int32_t* d_capacities, const int32_t* d_cap_off, int64_t* d_out,
                            void* hip_stream);
+
+/* Cost of a packing (Section 1, formal definition; Section 6.1): the sum of
+ * the capacities of its bins, sum over b < nbins of capacities[bin_types[b]]
+ * (host pointers; bin_types may be NULL when nbins is 0).  Returns the cost
+ * (>= 0) or a negative VSBPP_E_* code: NULL, SIZE (nbins < 0, n outside
+ * 1..16, or a type index outside [0, n)), CAPS. */
+int64_t vsbpp_cost(const int32_t* bin_types, int32_t nbins, const int32_t* capacities,
+                   int32_t n);
+
+/* Lower bound on the optimum cost of one instance (host pointers,
+ * synchronous, no device use): max(LB_cap, LB_big).  The bins of any packing
+ * hold the total weight W, and their capacities are a sum of B_1..B_n with
+ * repetition, so the cost is at least LB_cap, the least such sum >= W
+ * (exact when B_n <= 2^20; above that W itself is returned for LB_cap).
+ * Items heavier than B_1/2 pairwise cannot share a bin, so the cost is also
+ * at least LB_big, the sum over those items of the smallest capacity
+ * holding each.  The same bounds as vsbpp_lower_bounds computes per
+ * instance on the device (whose LB_cap is exact only when B_n <= 8192).
+ * Returns the bound or a negative code: NULL, SIZE (m < 1, n outside
+ * 1..16), CAPS, WEIGHT. */
+int64_t vsbpp_lower_bound(const int32_t* weights, int32_t m, const int32_t* capacities,
+                          int32_t n);
+
+/* Loads a trained scorer: the file holds one vsbpp_model exactly as laid
+ * out above (little-endian, sizeof(vsbpp_model) bytes; the layout the
+ * trainer exports).  Checks the size, 1 <= n_out <= 16 and that every weight
+ * and bias in use is finite, then copies the model to device memory of the
+ * current device; *out receives that device pointer, ready for
+ * vsbpp_pack_batch_ex and vsbpp_plan_create_ex.  The caller releases it with
+ * vsbpp_model_free.  Returns VSBPP_OK, VSBPP_E_NULL, VSBPP_E_MODEL (file
+ * missing or unreadable, or a failed check), VSBPP_E_DEVICE or
+ * VSBPP_E_NOMEM; *out is NULL on error. */
+int32_t vsbpp_model_load(const char* path, vsbpp_model** out);
+/* Frees a model returned by vsbpp_model_load (NULL is ignored). */
+void vsbpp_model_free(vsbpp_model* d_model);
 
 /* Best of a batch: writes d_out[0] = min cost and d_out[1] = the lowest index
  * reaching it over d_cost[0..num-1] (device pointers, asynchronous on

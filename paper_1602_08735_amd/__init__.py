@@ -24,7 +24,7 @@ TYPE_SMALLEST_FIT, TYPE_LARGEST = 0, 1
 
 ERRORS = {
     -1: "E_NULL", -2: "E_SIZE", -3: "E_CAPS", -4: "E_WEIGHT", -5: "E_HEURISTIC",
-    -6: "E_OPTION", -7: "E_DEVICE", -8: "E_NOMEM",
+    -6: "E_OPTION", -7: "E_DEVICE", -8: "E_NOMEM", -9: "E_MODEL",
 }
 
 # exported symbols, as declared in include/vsbpp.h
@@ -35,7 +35,8 @@ EXPORTS = (
     "vsbpp_pack_batch_ex", "vsbpp_rollout_labels", "vsbpp_trainer_create",
     "vsbpp_trainer_step", "vsbpp_trainer_gradient", "vsbpp_trainer_device_model",
     "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
-    "vsbpp_plan_create_ex", "vsbpp_exact_batch",
+    "vsbpp_plan_create_ex", "vsbpp_exact_batch", "vsbpp_cost", "vsbpp_lower_bound",
+    "vsbpp_model_load", "vsbpp_model_free",
 )
 
 
@@ -93,6 +94,14 @@ def lib():
         L.vsbpp_last_error.argtypes = []
         L.vsbpp_device_ok.restype = i32
         L.vsbpp_device_ok.argtypes = []
+        L.vsbpp_cost.restype = i64
+        L.vsbpp_cost.argtypes = [vp, i32, vp, i32]
+        L.vsbpp_lower_bound.restype = i64
+        L.vsbpp_lower_bound.argtypes = [vp, i32, vp, i32]
+        L.vsbpp_model_load.restype = i32
+        L.vsbpp_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.vsbpp_model_free.restype = None
+        L.vsbpp_model_free.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -109,6 +118,51 @@ def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMAL
     o.active_limit = active_limit
     o.downsize = int(downsize)
     return o
+
+
+def cost(bin_types, caps) -> int:
+    """vsbpp_cost: the total capacity of the bins of a packing."""
+    t = np.ascontiguousarray(np.asarray(bin_types, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(caps, dtype=np.int32))
+    rc = lib().vsbpp_cost(t.ctypes.data if t.size else None, int(t.size), c.ctypes.data,
+                          int(c.size))
+    if rc < 0:
+        raise VsbppError(rc, "vsbpp_cost")
+    return int(rc)
+
+
+def lower_bound(weights, caps) -> int:
+    """vsbpp_lower_bound: max(LB_cap, LB_big) of one instance (host)."""
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(caps, dtype=np.int32))
+    rc = lib().vsbpp_lower_bound(w.ctypes.data if w.size else None, int(w.size), c.ctypes.data,
+                                 int(c.size))
+    if rc < 0:
+        raise VsbppError(rc, "vsbpp_lower_bound")
+    return int(rc)
+
+
+class DeviceModel:
+    """A scorer loaded by vsbpp_model_load into device memory; ``ptr`` is
+    the device pointer the learned calls take.  Freed by close()."""
+
+    def __init__(self, path: str):
+        h = ctypes.c_void_p()
+        rc = lib().vsbpp_model_load(os.fsencode(path), ctypes.byref(h))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_model_load")
+        self.ptr = h.value
+
+    def close(self) -> None:
+        if getattr(self, "ptr", None):
+            lib().vsbpp_model_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def strerror(code: int) -> str:

@@ -1,7 +1,7 @@
 // Exact optimum of small VSBPP instances (m <= 12 items), a batch at a time.
 //
-// Cost model of the problem statement (Section 2): a bin of type k costs its
-// capacity B_k, a packing costs the sum over its used bins.  A block of items
+// Cost model of the problem statement (Section 1, formal definition): a bin
+// of type k costs its capacity B_k, a packing costs the sum over its used bins.  A block of items
 // (the contents of one bin) therefore costs the smallest capacity that holds
 // its total weight, and the optimum is the cheapest partition of the items
 // into blocks.  The kernel evaluates it by dynamic programming over item

@@ -73,23 +73,17 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     return VSBPP_E_SIZE;
   if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
   vsbpp_options o = vsbpp::resolve_options(opt);
-  if (o.type_rule == VSBPP_TYPE_LEARNED) {
-    if (!d_model) return VSBPP_E_NULL;
-    o.type_rule = VSBPP_TYPE_SMALLEST_FIT;  // for the shared checks below
-    int32_t rc = vsbpp::check_options_public(o);
-    if (rc != VSBPP_OK) return rc;
-    o.type_rule = VSBPP_TYPE_LEARNED;
-  } else {
-    int32_t rc = vsbpp::check_options_public(o);
-    if (rc != VSBPP_OK) return rc;
-  }
+  const bool learned = o.type_rule == VSBPP_TYPE_LEARNED;
+  if (learned) o.type_rule = VSBPP_TYPE_SMALLEST_FIT;  // for the shared checks below
   {
-    const int32_t rc = vsbpp::check_heuristic_options_public(o, heuristic);
+    int32_t rc = vsbpp::check_options_public(o);
+    if (rc == VSBPP_OK) rc = vsbpp::check_heuristic_options_public(o, heuristic);
     if (rc != VSBPP_OK) return rc;
   }
-  const bool ext = o.type_rule == VSBPP_TYPE_LEARNED ||
-                   (dec && (dec->src || dec->force || dec->features || dec->info));
+  if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
+  const bool ext = learned || (dec && (dec->src || dec->force || dec->features || dec->info));
   if (ext && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
+  if (learned && !d_model) return VSBPP_E_MODEL;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
   vsbpp::BatchArgs a{};
   a.w = b->weights;

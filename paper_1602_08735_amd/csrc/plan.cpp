@@ -220,13 +220,13 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   vsbpp_options o = vsbpp::resolve_options(opt);
   const bool learned = o.type_rule == VSBPP_TYPE_LEARNED;
   if (learned) {
-    if (!d_model) return VSBPP_E_NULL;
     if (heuristic > VSBPP_WF) return VSBPP_E_OPTION;
     o.type_rule = VSBPP_TYPE_SMALLEST_FIT;  // shared checks below
   }
   int32_t rc = vsbpp::check_options_public(o);
   if (rc == VSBPP_OK) rc = vsbpp::check_heuristic_options_public(o, heuristic);
   if (rc != VSBPP_OK) return rc;
+  if (learned && !d_model) return VSBPP_E_MODEL;
   if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
 

@@ -361,6 +361,7 @@ const char* vsbpp_strerror(int32_t code) {
     case VSBPP_E_OPTION: return "invalid option";
     case VSBPP_E_DEVICE: return "no usable gfx950 device, or a HIP runtime error";
     case VSBPP_E_NOMEM: return "device memory allocation failed";
+    case VSBPP_E_MODEL: return "learned type rule without a usable model";
     default: return code >= 0 ? "ok" : "unknown error";
   }
 }

@@ -162,3 +162,131 @@ def test_exact_batch_host_checks(V):
     if not V.device_ok():
         d.max_items, d.max_types, d.max_capacity = 12, 3, 100
         assert L.vsbpp_exact_batch(ctypes.byref(d), None) == -7
+
+
+# ---------------------------------------------------------------------------
+# Cost and lower bound of the formal problem (host calls, no device) and the
+# model loader's checks.
+# ---------------------------------------------------------------------------
+def test_cost_of_a_packing(V):
+    # Section 1: a packing costs the sum of its bins' capacities
+    assert V.cost([0, 1, 2, 2], [10, 7, 4]) == 10 + 7 + 4 + 4
+    assert V.cost([], [10, 7, 4]) == 0
+    caps = np.array([2**31 - 1, 2**31 - 2], dtype=np.int32)
+    assert V.cost([0] * 5 + [1] * 3, caps) == 5 * (2**31 - 1) + 3 * (2**31 - 2)
+    L = V.lib()
+    c = np.array([10, 7, 4], dtype=np.int32)
+    t = np.array([0, 3], dtype=np.int32)
+    assert L.vsbpp_cost(t.ctypes.data, 2, None, 3) == -1
+    assert L.vsbpp_cost(None, 2, c.ctypes.data, 3) == -1
+    assert L.vsbpp_cost(t.ctypes.data, -1, c.ctypes.data, 3) == -2
+    assert L.vsbpp_cost(t.ctypes.data, 2, c.ctypes.data, 0) == -2
+    assert L.vsbpp_cost(t.ctypes.data, 2, c.ctypes.data, 17) == -2
+    assert L.vsbpp_cost(t.ctypes.data, 2, c.ctypes.data, 3) == -2  # type 3 of 3
+    bad = np.array([7, 10, 4], dtype=np.int32)
+    assert L.vsbpp_cost(t.ctypes.data, 1, bad.ctypes.data, 3) == -3
+
+
+def test_cost_matches_oracle_packings(V, orc):
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        n = int(rng.integers(1, 8))
+        caps = np.sort(rng.choice(np.arange(20, 400), n, replace=False))[::-1]
+        w = rng.integers(1, caps[0] + 1, int(rng.integers(1, 60)))
+        for h in ("FF", "BF", "WF", "H1", "H2"):
+            r = orc.pack(w, caps, h, seed=3)
+            assert V.cost(r.bin_types, caps) == r.cost
+
+
+def test_lower_bound_hand_values(V):
+    # worked example C: total 21 = 7 + 7 + 7 with caps {10, 7, 4}
+    assert V.lower_bound([3, 6, 4, 2, 5, 1], [10, 7, 4]) == 21
+    # total 13 with caps {10, 7}: reachable sums 0, 7, 10, 14, 17, ... -> 14
+    assert V.lower_bound([6, 7], [10, 7]) == 14
+    # LB_big: three items heavier than B_1/2 = 50, smallest holders 60, 60, 100
+    assert V.lower_bound([51, 55, 90, 1], [100, 60, 40]) == 220
+    # one type: ceil(total / B) * B
+    assert V.lower_bound([3, 3, 3], [4]) == 12
+    # capacities above the residue limit: LB_cap is the total weight
+    big = [2**31 - 1, 2**30 + 5]
+    assert V.lower_bound([5, 6], big) == 11
+
+
+def test_lower_bound_matches_oracle(V, orc):
+    rng = np.random.default_rng(17)
+    for _ in range(300):
+        n = int(rng.integers(1, 9))
+        caps = np.sort(rng.choice(np.arange(2, 300), n, replace=False))[::-1]
+        w = rng.integers(1, caps[0] + 1, int(rng.integers(1, 40)))
+        want = max(orc.lb_cap(w, caps), orc.lb_big(w, caps))
+        assert V.lower_bound(w, caps) == want == orc.lower_bound(w, caps), (w, caps)
+
+
+def test_lower_bound_checks(V):
+    L = V.lib()
+    c = np.array([10, 7], dtype=np.int32)
+    w = np.array([1, 2, 11], dtype=np.int32)
+    assert L.vsbpp_lower_bound(None, 3, c.ctypes.data, 2) == -1
+    assert L.vsbpp_lower_bound(w.ctypes.data, 0, c.ctypes.data, 2) == -2
+    assert L.vsbpp_lower_bound(w.ctypes.data, 2, c.ctypes.data, 17) == -2
+    bad = np.array([7, 7], dtype=np.int32)
+    assert L.vsbpp_lower_bound(w.ctypes.data, 2, bad.ctypes.data, 2) == -3
+    assert L.vsbpp_lower_bound(w.ctypes.data, 3, c.ctypes.data, 2) == -4
+
+
+def test_model_load_checks(V, tmp_path):
+    L = V.lib()
+    out = ctypes.c_void_p(123)
+    assert L.vsbpp_model_load(b"x", None) == -1
+    assert L.vsbpp_model_load(None, ctypes.byref(out)) == -1 and out.value is None
+    assert L.vsbpp_model_load(str(tmp_path / "missing.bin").encode(), ctypes.byref(out)) == -9
+    good = open(os.path.join(ROOT, "paper_1602_08735_amd", "models", "scorer_BF.bin"),
+                "rb").read()
+    assert len(good) == ctypes.sizeof(V.Model)
+    cases = {"short": good[:-1], "long": good + b"\0"}
+    m = V.Model.from_bytes(good)
+    m.n_out = 0
+    cases["n_out0"] = m.to_bytes()
+    m = V.Model.from_bytes(good)
+    m.n_out = 17
+    cases["n_out17"] = m.to_bytes()
+    m = V.Model.from_bytes(good)
+    m.b2[3] = float("nan")
+    cases["nan_bias"] = m.to_bytes()
+    m = V.Model.from_bytes(good)
+    m.w1[7] = 0x7F80  # +inf as bf16
+    cases["inf_weight"] = m.to_bytes()
+    for name, data in cases.items():
+        p = tmp_path / f"{name}.bin"
+        p.write_bytes(data)
+        out = ctypes.c_void_p(123)
+        assert L.vsbpp_model_load(str(p).encode(), ctypes.byref(out)) == -9, name
+        assert out.value is None, name
+    # rows of W3 beyond n_out are not used and not checked
+    m = V.Model.from_bytes(good)
+    m.w3[64 * m.n_out] = 0x7FC0
+    p = tmp_path / "unused_rows.bin"
+    p.write_bytes(m.to_bytes())
+    if not V.device_ok():
+        assert L.vsbpp_model_load(str(p).encode(), ctypes.byref(out)) == -7
+    L.vsbpp_model_free(None)
+
+
+def test_learned_rule_without_model(V):
+    L = V._learn_lib()
+    d = V._BatchDesc()
+    d.num_instances = 2
+    for f in ("weights", "item_off", "capacities", "cap_off", "assignment", "bin_types",
+              "nbins", "cost"):
+        setattr(d, f, 16)
+    d.max_items, d.max_types, d.max_capacity = 10, 3, 100
+    o = V.options(type_rule=V.TYPE_LEARNED)
+    assert L.vsbpp_pack_batch_ex(ctypes.byref(d), 0, ctypes.byref(o), None, None, None) == -9
+    out = ctypes.c_void_p()
+    assert L.vsbpp_plan_create_ex(ctypes.byref(d), 1, ctypes.byref(o), None, None, 0,
+                                  ctypes.byref(out)) == -9
+    # option errors come first, and the scorer is for plain heuristics only
+    bad = V.options(type_rule=V.TYPE_LEARNED, s2=9)
+    assert L.vsbpp_pack_batch_ex(ctypes.byref(d), 0, ctypes.byref(bad), None, None, None) == -6
+    assert L.vsbpp_plan_create_ex(ctypes.byref(d), 3, ctypes.byref(o), None, None, 0,
+                                  ctypes.byref(out)) == -6

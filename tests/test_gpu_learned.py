@@ -135,6 +135,58 @@ def test_lower_bounds(V, orc):
         assert o[i, 2] == orc.lb_big(w, caps)
 
 
+def test_host_lower_bound_matches_device_and_oracle(V, orc):
+    """vsbpp_lower_bound (host) against vsbpp_lower_bounds (device) and the
+    oracle, on instances whose smallest capacity keeps both exact."""
+    import torch
+
+    rng = np.random.default_rng(18)
+    b = inputs.random_batch(rng, 200, 1, 300, b1_hi=5000)
+    db = V.DeviceBatch(b)
+    out = torch.empty(3 * b.n_instances, dtype=torch.int64, device="cuda")
+    V.lower_bounds(db, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().reshape(-1, 3)
+    for i in range(b.n_instances):
+        w, caps, _ = b.instance(i)
+        assert caps[-1] <= 8192
+        host = V.lower_bound(w, caps)
+        assert host == max(int(o[i, 1]), int(o[i, 2])) == orc.lower_bound(w, caps), i
+
+
+def test_model_load_drives_the_scorer(V, orc):
+    """A committed scorer through vsbpp_model_load runs the learned rule bit
+    for bit as the oracle does with the same file, and vsbpp_cost of every
+    packing equals the cost the kernel reports."""
+    import os
+
+    import torch
+
+    from conftest import ROOT
+
+    path = os.path.join(ROOT, "paper_1602_08735_amd", "models", "scorer_WF.bin")
+    dm = V.DeviceModel(path)
+    with open(path, "rb") as f:
+        om = orc.Model.from_buffer_copy(f.read())
+    b = c2_batch(40, 500, 19)
+    db = V.DeviceBatch(b)
+    V.pack_batch_ex(db, "WF", model_ptr=dm.ptr, type_rule=V.TYPE_LEARNED)
+    torch.cuda.synchronize()
+    a = db.assignment.cpu().numpy()
+    t = db.bin_types.cpu().numpy()
+    nb = db.nbins.cpu().numpy()
+    cost = db.cost.cpu().numpy()
+    for i in range(b.n_instances):
+        w, caps, _ = b.instance(i)
+        r = orc.pack(w, caps, "WF", type_rule=orc.TYPE_LEARNED, model=om)
+        lo, hi = int(b.item_off[i]), int(b.item_off[i + 1])
+        assert int(nb[i]) == r.nbins and int(cost[i]) == r.cost, i
+        assert np.array_equal(a[lo:hi], r.assignment), i
+        assert np.array_equal(t[lo:lo + r.nbins], r.bin_types), i
+        assert V.cost(t[lo:lo + int(nb[i])], caps) == int(cost[i]), i
+    dm.close()
+
+
 def test_training_gradient_matches_float64(V, L):
     import torch
 

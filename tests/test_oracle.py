@@ -3,12 +3,13 @@ outputs, the paper's structural tables, hand-worked examples, closed forms,
 brute-force optima and property checks.  CPU only."""
 import itertools
 import math
+import os
 
 import numpy as np
 import pytest
 
 from checks import check_valid, replay_plain
-from conftest import golden
+from conftest import ROOT, golden
 from paper_1602_08735_amd import inputs
 
 HEUR = ("FF", "BF", "WF", "H1", "H2")
@@ -53,6 +54,22 @@ def test_h2_criterion_digits_of_known_outputs(orc):
             d = int(frac)
             frac -= d
             assert orc.criterion_digit(g["seed"], k, t) == d, (k, t)
+            # the closed form the public header states for this draw
+            assert ((3 ** (t + 1) * (int(x) >> 32)) >> 32) % 3 == d, (k, t)
+
+
+def test_header_states_the_draws_the_oracle_makes():
+    """The C header documents Rule 3's draws as the oracle makes them: H1 at
+    counter q, H2 one output per permutation packing at counter I*S! + r with
+    placement t taking floor(3^(t+1)*h/2^32) mod 3."""
+    import re
+
+    with open(os.path.join(ROOT, "include", "vsbpp.h")) as f:
+        text = re.sub(r"\s+", " ", f.read())
+    assert "counter I*S! + r" in text
+    assert "floor(3^(t+1)*h/2^32) mod 3" in text
+    assert "floor(3*hi32(x)/2^32)" in text
+    assert "(I*S! + r)*S + t" not in text
 
 
 def test_h2_criterion_digits_joint_uniform(orc):
