@@ -124,6 +124,15 @@ typedef struct vsbpp_options {
                                included).  0 (default) or 1, else
                                VSBPP_E_OPTION; not with decision-hook entries
                                that name a source instance.                   */
+  int32_t criterion_rule;   /* H1 only: 0 (default) Rule 3 draws FF/BF/WF with
+                               equal probability; 1 a trained network picks
+                               the criterion wherever FF, BF and WF would put
+                               the item into different bins (see the learned
+                               criterion below).  1 needs a model, so only
+                               vsbpp_pack_batch_ex and vsbpp_plan_create_ex
+                               take it (the other calls: VSBPP_E_MODEL);
+                               with another heuristic or a forced criterion:
+                               VSBPP_E_OPTION.                                */
 } vsbpp_options;
 
 void vsbpp_options_init(vsbpp_options* opt);
@@ -220,13 +229,19 @@ typedef struct vsbpp_batch {
  * resident workgroups taking instances from a device work counter.  lpt = 1
  * processes instances by decreasing item count (largest first, for uneven
  * batches; batches up to 8192 instances).  waves_per_block: FF/BF/WF
- * wavefronts (one instance each) per workgroup, 1..8.  block_threads: H1/H2
- * workgroup size (H2: a multiple of roundup(s2!, 64)). */
+ * wavefronts per workgroup, 1..8 (1..4 with fewer than 64 lanes per
+ * instance).  block_threads: H1/H2 workgroup size (H2: a multiple of
+ * roundup(s2!, 64)).  lanes_per_instance: FF/BF/WF lanes that test one
+ * instance's bins, 64 (one instance per wavefront; 0 means 64), 32 or 16
+ * (two or four instances per wavefront, stepping through their items
+ * together; only for runs with B_1 <= 32767, m <= 65535, no scorer, hooks
+ * or bound on the open bins, whose bins fit LDS, else VSBPP_E_OPTION). */
 typedef struct vsbpp_launch {
   int32_t mode;
   int32_t lpt;
   int32_t waves_per_block;
   int32_t block_threads;
+  int32_t lanes_per_instance;
 } vsbpp_launch;
 
 enum {
@@ -312,11 +327,10 @@ int32_t vsbpp_exact_batch(const vsbpp_batch* batch, void* hip_stream);
 /* product with the fp32 reciprocal; the mean in feature 2 is the fp32      */
 /* quotient (sum / count), then times 1/B_1.                                */
 /* Network: h1 = relu(W1 x + b1) (64), h2 = relu(W2 h1 + b2) (64),           */
-/* z = W3 h2 + b3 (n_out).  A hidden unit is its bias followed by a chain of */
-/* fp32 fused multiply-adds over its inputs in index order.  Output k is     */
-/* b3[k] + p_0 + ... + p_7 (fp32 additions in that order), where p_g is a    */
-/* fused multiply-add chain from 0 over inputs 8g..8g+7.  So results are     */
-/* reproducible bit for bit.  Decision: the type k < min(n, n_out) holding   */
+/* z = W3 h2 + b3 (n_out).  Every unit, hidden or output, is its bias       */
+/* followed by a chain of fp32 fused multiply-adds over its inputs in index  */
+/* order, so results are reproducible bit for bit.                           */
+/* Decision: the type k < min(n, n_out) holding                              */
 /* the item with the largest z, lowest k on ties; decisions where only B_1   */
 /* holds the item are not scored.                                            */
 /* ------------------------------------------------------------------------ */
@@ -354,11 +368,33 @@ typedef struct vsbpp_decisions {
   int32_t* info;
 } vsbpp_decisions;
 
+/* Learned criterion of the first heuristic (opt->criterion_rule = 1, Section
+ * 6.3's Rule 3 replaced where it matters).  At a placement where First, Best
+ * and Worst Fit would choose different bins of the packer, the network
+ * (n_out >= 3; outputs 0, 1, 2 score FF, BF, WF) is evaluated on these fp32
+ * features, the rest 0 ("a / b" is a times the fp32 reciprocal of b):
+ *   0  w / B_1                 1  t / k (position t of a sublist of k items)
+ *   2  room left in FF's bin after the item / B_1
+ *   3  the same for BF's bin   4  the same for WF's bin
+ *   5  bins the item fits / 16 6  bins in the packer (Rule 2 and 5 bins
+ *                                 included) / 32
+ * and the criterion with the largest score is used, lowest on ties.  Where
+ * the three agree or nothing fits, the criterion does not change the
+ * placement and Rule 3's draw stands; non-finite scores also keep the draw.
+ * The network's arithmetic is that of the bin-type scorer.  A model with
+ * fewer than 3 outputs gives VSBPP_E_MODEL in every instance's d_nbins. */
+
 /* vsbpp_pack_batch with a scorer (d_model: device pointer to a vsbpp_model,
  * e.g. from vsbpp_model_load, required when opt->type_rule is
- * VSBPP_TYPE_LEARNED -- VSBPP_E_MODEL when it is NULL -- else ignored) and
- * decision hooks (dec may be NULL).  Plain FF/BF/WF only when either is
- * used.  Asynchronous on hip_stream, no allocation. */
+ * VSBPP_TYPE_LEARNED or opt->criterion_rule is 1 -- VSBPP_E_MODEL when it is
+ * NULL -- else ignored) and decision hooks (dec may be NULL).  The bin-type
+ * scorer and the hooks above are for plain FF/BF/WF.  With H1, dec may carry
+ * features and info only (src and force: VSBPP_E_OPTION), in another
+ * layout: for the item at position q of instance i (offset off_i of its
+ * items), info[off_i + q] = 1 when the placement was contested (the three
+ * criteria choose different bins) and 0 otherwise, and a contested
+ * placement's 16 features go to features[16*(off_i + q) ..].  Asynchronous
+ * on hip_stream, no allocation. */
 int32_t vsbpp_pack_batch_ex(const vsbpp_batch* batch, int32_t heuristic,
                             const vsbpp_options* opt, const vsbpp_model* d_model,
                             const vsbpp_decisions* dec, void* hip_stream);
@@ -456,6 +492,16 @@ void vsbpp_model_free(vsbpp_model* d_model);
  * reaching it over d_cost[0..num-1] (device pointers, asynchronous on
  * hip_stream).  Used to keep the best of several orderings of one instance. */
 int32_t vsbpp_best_of(const int64_t* d_cost, int32_t num, int64_t* d_out, void* hip_stream);
+
+/* Achievable on-chip peaks of the current device, measured now by two
+ * stream kernels (synchronous, a few milliseconds): out[0] = LDS read
+ * bandwidth in bytes/s (16-byte reads at unit lane stride, no bank
+ * conflicts, 16 workgroups of 256 threads per compute unit), out[1] = 32-bit
+ * integer VALU lane-operations/s (independent add/xor/min chains).
+ * The packing kernels' roofline fractions are taken against these next to
+ * the published peaks.  Returns VSBPP_OK, VSBPP_E_NULL, VSBPP_E_DEVICE or
+ * VSBPP_E_NOMEM. */
+int32_t vsbpp_measure_peaks(double* out);
 
 /* Text of an error code (static storage). */
 const char* vsbpp_strerror(int32_t code);

@@ -82,6 +82,7 @@ class _Opts(ctypes.Structure):
         ("trace_count", ctypes.POINTER(ctypes.c_int32)),
         ("active_limit", ctypes.c_int32),
         ("downsize", ctypes.c_int32),
+        ("criterion_rule", ctypes.c_int32),
     ]
 
 
@@ -195,7 +196,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
          type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
          order=None, model: "Model | None" = None, force_event: int = -1,
          force_types=(0, 0), trace: bool = False, active_limit: int = 0,
-         downsize: bool = False) -> Packing:
+         downsize: bool = False, criterion_rule: int = 0) -> Packing:
     w = _i32(weights)
     c = _i32(caps)
     m = int(w.size)
@@ -210,6 +211,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     o.force_t1, o.force_t2 = int(force_types[0]), int(force_types[1])
     o.active_limit = int(active_limit)
     o.downsize = int(downsize)
+    o.criterion_rule = int(criterion_rule)
     tr_arr = None
     tr_count = ctypes.c_int32(0)
     if trace:

@@ -255,6 +255,11 @@ static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_
     if (o->force_crit < -1 || o->force_crit > ORC_WF) return ORC_E_OPTION;
     if (o->active_limit < 0 || (o->active_limit > 0 && heuristic > ORC_WF)) return ORC_E_OPTION;
     if (o->downsize != 0 && o->downsize != 1) return ORC_E_OPTION;
+    if (o->criterion_rule != 0 && o->criterion_rule != 1) return ORC_E_OPTION;
+    if (o->criterion_rule == 1 &&
+        (heuristic != ORC_H1 || o->force_crit != -1 || !o->model || o->model->n_out < 3 ||
+         o->model->n_out > ORC_MAX_OUT))
+      return ORC_E_OPTION;
     if (o->order) {
       /* must be a permutation of [0,m) */
       char* seen = (char*)calloc((size_t)m, 1);
@@ -292,10 +297,10 @@ static float bf16_to_f32(uint16_t h) {
 
 static float relu(float v) { return v > 0.0f ? v : 0.0f; }
 
-/* Hidden outputs are their bias followed by a chain of fused multiply-adds
- * over the inputs in index order (fp32), then ReLU.  An output score z[k] is
- * its bias plus, in order g = 0..7, the partial sums p_g = fused
- * multiply-add chain over inputs 8g..8g+7 started from 0. */
+/* Every unit -- hidden or output -- is its bias followed by a chain of fused
+ * multiply-adds over its inputs in index order (fp32); hidden units then
+ * take ReLU.  This fixes the rounding of each score, so the scores, and the
+ * integer decisions they drive, are reproducible bit for bit. */
 void orc_mlp_forward(const orc_model* mdl, const float* x, float* z) {
   float h1[ORC_HIDDEN], h2[ORC_HIDDEN];
   for (int l = 0; l < ORC_HIDDEN; ++l) {
@@ -310,12 +315,7 @@ void orc_mlp_forward(const orc_model* mdl, const float* x, float* z) {
   }
   for (int k = 0; k < mdl->n_out; ++k) {
     float acc = mdl->b3[k];
-    for (int g = 0; g < 8; ++g) {
-      float p = 0.0f;
-      for (int r = 0; r < 8; ++r)
-        p = fmaf(bf16_to_f32(mdl->w3[k * ORC_HIDDEN + 8 * g + r]), h2[8 * g + r], p);
-      acc = acc + p;
-    }
+    for (int j = 0; j < ORC_HIDDEN; ++j) acc = fmaf(bf16_to_f32(mdl->w3[k * ORC_HIDDEN + j]), h2[j], acc);
     z[k] = acc;
   }
 }
@@ -475,7 +475,7 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
   orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize};
+  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize, 0};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label = -1;
   if (rc >= 0 && d < count) {
@@ -487,7 +487,7 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
       if (!((feasible >> k1) & 1u)) continue;
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < n; ++k2) {
-        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize};
+        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize, 0};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }
@@ -509,6 +509,64 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
   return label;
 }
 
+/* Learned criterion for the first heuristic (an alternative to Rule 3's
+ * equal-probability draw, Section 6.3): where First, Best and Worst Fit would
+ * put the item into different bins of the packer, a network scores the three
+ * criteria from features of the placement and the best score wins (lowest
+ * criterion on ties).  Where they agree, or nothing fits, the criterion does
+ * not change the placement and the draw `drawn` stands; a non-finite score
+ * also falls back to the draw.  Features (fp32; "a / b" is a times the fp32
+ * reciprocal of b), the rest zero:
+ *   0  w / B_1            1  t / k (position t of a sublist of k items)
+ *   2  room left in First Fit's bin after the item / B_1
+ *   3  the same for Best Fit's bin    4  the same for Worst Fit's bin
+ *   5  bins the item fits / 16        6  bins in the packer / 32        */
+static int32_t h1_learned_criterion(const opacker* p, const int32_t* caps, int32_t w,
+                                    int32_t t, int32_t k, int32_t q, int32_t drawn,
+                                    const orc_opts* o) {
+  int32_t bff = -1, bbf = -1, bwf = -1, nfit = 0;
+  int64_t abf = 0, awf = 0;
+  for (int32_t b = 0; b < p->nb; ++b) {
+    const int64_t room = (int64_t)caps[p->b[b].type] - p->b[b].load;
+    if (room < w) continue;
+    const int64_t after = room - w;
+    ++nfit;
+    if (bff < 0) bff = b;
+    if (bbf < 0 || after < abf) { bbf = b; abf = after; }
+    if (bwf < 0 || after > awf) { bwf = b; awf = after; }
+  }
+  if (bff < 0 || (bff == bbf && bbf == bwf)) return drawn;
+  const float inv_b1 = 1.0f / (float)caps[0];
+  float x[ORC_NFEAT];
+  memset(x, 0, sizeof x);
+  const int64_t aff = (int64_t)caps[p->b[bff].type] - p->b[bff].load - w;
+  x[0] = (float)w * inv_b1;
+  x[1] = (float)t * (1.0f / (float)k);
+  x[2] = (float)aff * inv_b1;
+  x[3] = (float)abf * inv_b1;
+  x[4] = (float)awf * inv_b1;
+  x[5] = (float)nfit * (1.0f / 16.0f);
+  x[6] = (float)p->nb * (1.0f / 32.0f);
+  float z[ORC_MAX_OUT];
+  orc_mlp_forward(o->model, x, z);
+  int32_t c = drawn;
+  if (isfinite(z[0]) && isfinite(z[1]) && isfinite(z[2])) {
+    c = 0;
+    if (z[1] > z[c]) c = 1;
+    if (z[2] > z[c]) c = 2;
+  }
+  if (o->trace && o->trace_count && *o->trace_count < o->trace_cap) {
+    orc_decision* d = &o->trace[(*o->trace_count)++];
+    d->position = q;
+    d->weight = w;
+    d->plain_type = drawn;
+    d->chosen = c;
+    d->feasible = 7u;
+    memcpy(d->feat, x, sizeof x);
+  }
+  return c;
+}
+
 /* First heuristic (Section 6.3).  Sublist I holds positions
  * [I*s1, min((I+1)*s1, m)); every sublist is its own packer that starts with
  * one empty bin of each type (Rule 2), takes its items in position order
@@ -525,6 +583,7 @@ static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
   int64_t* smin = (int64_t*)malloc(sizeof(int64_t) * (size_t)s1);
   int32_t base = 0;
   *cost = 0;
+  if (o->criterion_rule == 1 && o->trace_count) *o->trace_count = 0;
   for (int32_t I = 0; I < l; ++I) {
     int32_t q0 = I * s1;
     int32_t k = (m - q0 < s1) ? m - q0 : s1;
@@ -539,6 +598,8 @@ static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
     for (int32_t t = 0; t < k; ++t) {
       int32_t c = o->force_crit >= 0 ? o->force_crit
                                      : orc_criterion(ck, (uint64_t)(q0 + t));
+      if (o->criterion_rule == 1)
+        c = h1_learned_criterion(&p, caps, w[items[t]], t, k, q0 + t, c, o);
       local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL);
     }
     base += emit_packer(&p, caps, items, local, k, base, assign, types, cost);
@@ -673,7 +734,7 @@ int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
 static int32_t orc_pack_run(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                             int32_t heuristic, const orc_opts* opt, int32_t* assign,
                             int32_t* types, int64_t* cost, orc_stats* stats) {
-  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0};
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0, 0};
   const orc_opts* o = opt ? opt : &def;
   if (!assign || !types || !cost) return ORC_E_NULL;
   int32_t rc = validate(w, m, caps, n, heuristic, o);

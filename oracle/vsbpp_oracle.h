@@ -43,7 +43,11 @@ typedef struct {
   float b3[ORC_MAX_OUT];
 } orc_model;
 
-/* one decision (an item that fits no open bin) of a plain FF/BF/WF run */
+/* one decision of a run: an item that fits no open bin in a plain FF/BF/WF
+ * run (chosen = type opened, plain_type = the base rule's type, feasible =
+ * types holding the item), or a placement of the first heuristic where the
+ * three criteria pick different bins under the learned criterion rule
+ * (chosen = criterion used, plain_type = Rule 3's draw, feasible = 7) */
 typedef struct {
   int32_t position;   /* position of the item in processing order      */
   int32_t weight;
@@ -74,6 +78,9 @@ typedef struct {
                              once (0: no limit); see run_plain               */
   int32_t downsize;       /* 1: after packing, every bin takes the smallest
                              type that holds its load (see downsize_bins)   */
+  int32_t criterion_rule; /* H1 only: 0 = Rule 3's draw; 1 = the model (n_out
+                             >= 3) picks FF/BF/WF where they differ (see
+                             h1_learned_criterion); needs force_crit = -1  */
 } orc_opts;
 
 typedef struct {

@@ -36,7 +36,7 @@ EXPORTS = (
     "vsbpp_trainer_step", "vsbpp_trainer_gradient", "vsbpp_trainer_device_model",
     "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
     "vsbpp_plan_create_ex", "vsbpp_exact_batch", "vsbpp_cost", "vsbpp_lower_bound",
-    "vsbpp_model_load", "vsbpp_model_free",
+    "vsbpp_model_load", "vsbpp_model_free", "vsbpp_measure_peaks",
 )
 
 
@@ -60,6 +60,7 @@ class Options(ctypes.Structure):
         ("order", ctypes.POINTER(ctypes.c_int32)),
         ("active_limit", ctypes.c_int32),
         ("downsize", ctypes.c_int32),
+        ("criterion_rule", ctypes.c_int32),
     ]
 
 
@@ -107,7 +108,8 @@ def lib():
 
 
 def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT,
-            force_crit: int = -1, active_limit: int = 0, downsize: bool = False) -> Options:
+            force_crit: int = -1, active_limit: int = 0, downsize: bool = False,
+            criterion_rule: int = 0) -> Options:
     o = Options()
     lib().vsbpp_options_init(ctypes.byref(o))
     o.seed = seed & (2**64 - 1)
@@ -117,6 +119,7 @@ def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMAL
     o.force_criterion = force_crit
     o.active_limit = active_limit
     o.downsize = int(downsize)
+    o.criterion_rule = int(criterion_rule)
     return o
 
 
@@ -163,6 +166,19 @@ class DeviceModel:
             self.close()
         except Exception:
             pass
+
+
+def measure_peaks() -> dict:
+    """vsbpp_measure_peaks: achievable LDS bytes/s and int32 VALU
+    lane-ops/s of the current device."""
+    out = (ctypes.c_double * 2)()
+    L = lib()
+    L.vsbpp_measure_peaks.restype = ctypes.c_int32
+    L.vsbpp_measure_peaks.argtypes = [ctypes.c_void_p]
+    rc = L.vsbpp_measure_peaks(ctypes.addressof(out))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_measure_peaks")
+    return {"lds_bytes_per_s": float(out[0]), "valu_int32_ops_per_s": float(out[1])}
 
 
 def strerror(code: int) -> str:
@@ -270,7 +286,8 @@ def best_of(cost_tensor, num: int, out_tensor, stream=None) -> None:
 
 class Launch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("lpt", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32), ("block_threads", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("lanes_per_instance", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -317,7 +334,7 @@ class Plan:
                  graph: bool = False, autotune: bool = False, seed: int = 0, s1: int = 10,
                  s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
                  use_order: bool = True, use_seeds: bool = True, model_ptr=None,
-                 active_limit: int = 0, downsize: bool = False):
+                 active_limit: int = 0, downsize: bool = False, criterion_rule: int = 0):
         L = _plan_lib()
         ptr = lambda x: None if x is None else x.data_ptr()
         self.db = db
@@ -326,11 +343,12 @@ class Plan:
             ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
             db.max_items, db.max_types, db.max_cap,
             ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
-        o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize)
+        o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize, criterion_rule)
         lp = None
         if launch is not None:
             lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
-                        launch.get("waves_per_block", 4), launch.get("block_threads", 256))
+                        launch.get("waves_per_block", 4), launch.get("block_threads", 256),
+                        launch.get("lanes_per_instance", 64))
         flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
         h = ctypes.c_void_p()
         if model_ptr is not None:
@@ -456,7 +474,8 @@ def _desc(db: DeviceBatch, use_order=True, use_seeds=True, outputs=True, num=Non
 def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force=None,
                   features=None, info=None, nbins=None, cost=None, seed: int = 0,
                   type_rule: int = TYPE_SMALLEST_FIT, stream=None,
-                  active_limit: int = 0, downsize: bool = False) -> None:
+                  active_limit: int = 0, downsize: bool = False, criterion_rule: int = 0,
+                  force_crit: int = -1) -> None:
     """vsbpp_pack_batch_ex.  With `src` (int32 tensor [E]) the batch has E
     entries reading instance src[e]; nbins/cost then receive E results (pass
     tensors of size E)."""
@@ -471,7 +490,8 @@ def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force
     if cost is not None:
         d.cost = cost.data_ptr()
     dec = _Decisions(ptr(src), ptr(force), ptr(features), ptr(info))
-    o = options(seed, type_rule=type_rule, active_limit=active_limit, downsize=downsize)
+    o = options(seed, type_rule=type_rule, active_limit=active_limit, downsize=downsize,
+                criterion_rule=criterion_rule, force_crit=force_crit)
     rc = L.vsbpp_pack_batch_ex(ctypes.byref(d), _heur(heuristic), ctypes.byref(o), model_ptr,
                                ctypes.byref(dec), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:

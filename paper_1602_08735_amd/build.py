@@ -9,8 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvsbpp.so")
-SOURCES = ["vsbpp_abi.cpp", "plan.cpp", "learn_abi.cpp", "host_calls.cpp", "plain_kernel.hip", "hps_kernels.hip",
-           "learn_kernels.hip", "bounds_kernel.hip", "exact_kernel.hip", "downsize_kernel.hip"]
+SOURCES = ["vsbpp_abi.cpp", "plan.cpp", "learn_abi.cpp", "host_calls.cpp", "plain_kernel.hip", "plain_seg_kernel.hip", "hps_kernels.hip",
+           "learn_kernels.hip", "bounds_kernel.hip", "exact_kernel.hip", "downsize_kernel.hip",
+           "peaks_kernel.hip"]
 HEADERS = ["device_common.h", "kernels.h", "host_internal.h", "learn.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

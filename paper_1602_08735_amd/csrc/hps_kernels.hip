@@ -116,10 +116,51 @@ struct LanePacker {
         best = min(best, key);
       }
     }
-    int b;
+    return apply(best < T::TOP ? (int)(best & (K)0xFF) : -1, w, scaps, n, type_rule);
+  }
+
+  // The bins First, Best and Worst Fit would choose for weight w (-1 when
+  // nothing fits; lowest index on ties), the number of bins it fits, and the
+  // room each choice leaves.  nbound as for place.
+  __device__ void choices(int32_t w, int nbound, int* bff, int* bbf, int* bwf, int* nfit,
+                          int32_t* aff, int32_t* abf, int32_t* awf) const {
+    using T = PK<K>;
+    K kb = ~(K)0, kw = ~(K)0;
+    int f = 0x7FFFFFFF, cnt = 0;
+    const int ng = (nbound + 3) >> 2;
+    for (int g = 0; g < ng; ++g) {
+      const int4 r4 = *reinterpret_cast<const int4*>(room + g * stride);
+      const int* rp = &r4.x;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t rm = kPacked ? (rp[j] & 0xFFFF) : rp[j];
+        const int32_t after = rm - w;
+        const int idx = (g << 2) + j;
+        const bool fits = after >= 0;
+        cnt += fits ? 1 : 0;
+        f = min(f, fits ? idx : 0x7FFFFFFF);
+        kb = min(kb, fits ? ((K)(uint32_t)after << T::SH) | (K)idx : ~(K)0);
+        kw = min(kw, fits ? ((K)(uint32_t)(T::R - after) << T::SH) | (K)idx : ~(K)0);
+      }
+    }
+    *nfit = cnt;
+    if (cnt == 0) {
+      *bff = *bbf = *bwf = -1;
+      return;
+    }
+    *bff = f;
+    *bbf = (int)(kb & (K)0xFF);
+    *bwf = (int)(kw & (K)0xFF);
+    *aff = room_at(f) - w;
+    *abf = (int32_t)(kb >> T::SH);
+    *awf = T::R - (int32_t)(kw >> T::SH);
+  }
+
+  // Puts weight w into bin b (b < 0: a new bin of the smallest type holding
+  // w, or B_1), then Rule 5.  Returns the bin index used.
+  __device__ int apply(int b, int32_t w, const int32_t* scaps, int n, int type_rule) {
     int32_t bcap, broom;
-    if (best < T::TOP) {
-      b = (int)(best & (K)0xFF);
+    if (b >= 0) {
       broom = room_at(b);
       bcap = cap_at(b);
     } else {
@@ -248,10 +289,89 @@ __device__ __forceinline__ uint64_t inst_seed(const BatchArgs& a, int inst) {
 }
 
 // ---------------------------------------------------------------------------
-// First heuristic (Section 6.3)
+// Learned criterion of the first heuristic: a network scores FF, BF and WF
+// where they would put the item into different bins (Rule 3's draw stands
+// where they agree, where nothing fits, and for non-finite scores).  Every
+// lane evaluates the network for its own packer: the weights sit in LDS as
+// fp32 and every lane reads the same word (a broadcast), the first hidden
+// layer is held in registers, and each second-layer unit, once formed, is
+// folded into the three output chains in unit order -- so every unit is its
+// bias followed by one fp32 fused-multiply-add chain over its inputs in
+// index order.
 // ---------------------------------------------------------------------------
-template <typename K>
-__global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
+struct H1Model {
+  float w1[64 * 16];  // [l][i]
+  float w2[64 * 64];  // [l][j]
+  float w3[3 * 64];   // [k][j]
+  float b1[64], b2[64], b3[4];
+  int32_t n_out;
+};
+constexpr size_t kH1ModelBytes = (sizeof(H1Model) + 15) & ~(size_t)15;
+
+__device__ __forceinline__ float bf16v(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+__device__ void stage_h1_model(const vsbpp_model* m, H1Model* s) {
+  for (int e = threadIdx.x; e < 64 * 16; e += blockDim.x) s->w1[e] = bf16v(m->w1[e]);
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) s->w2[e] = bf16v(m->w2[e]);
+  for (int e = threadIdx.x; e < 3 * 64; e += blockDim.x) s->w3[e] = bf16v(m->w3[e]);
+  for (int e = threadIdx.x; e < 64; e += blockDim.x) {
+    s->b1[e] = m->b1[e];
+    s->b2[e] = m->b2[e];
+    if (e < 3) s->b3[e] = m->b3[e];
+  }
+  if (threadIdx.x == 0) s->n_out = m->n_out;
+}
+
+// the criterion the network picks for features x, or `drawn`
+__device__ int h1_score(const H1Model* md, const float (&x)[16], int drawn) {
+  float h1[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    float acc = md->b1[l];
+#pragma unroll
+    for (int i = 0; i < 16; i += 4) {
+      const float4 wv = *reinterpret_cast<const float4*>(&md->w1[l * 16 + i]);
+      acc = __builtin_fmaf(wv.x, x[i], acc);
+      acc = __builtin_fmaf(wv.y, x[i + 1], acc);
+      acc = __builtin_fmaf(wv.z, x[i + 2], acc);
+      acc = __builtin_fmaf(wv.w, x[i + 3], acc);
+    }
+    h1[l] = acc > 0.0f ? acc : 0.0f;
+  }
+  float z0 = md->b3[0], z1 = md->b3[1], z2 = md->b3[2];
+  for (int l = 0; l < 64; ++l) {
+    float acc = md->b2[l];
+#pragma unroll
+    for (int j = 0; j < 64; j += 4) {
+      const float4 wv = *reinterpret_cast<const float4*>(&md->w2[l * 64 + j]);
+      acc = __builtin_fmaf(wv.x, h1[j], acc);
+      acc = __builtin_fmaf(wv.y, h1[j + 1], acc);
+      acc = __builtin_fmaf(wv.z, h1[j + 2], acc);
+      acc = __builtin_fmaf(wv.w, h1[j + 3], acc);
+    }
+    const float h2 = acc > 0.0f ? acc : 0.0f;
+    z0 = __builtin_fmaf(md->w3[l], h2, z0);
+    z1 = __builtin_fmaf(md->w3[64 + l], h2, z1);
+    z2 = __builtin_fmaf(md->w3[128 + l], h2, z2);
+  }
+  if (!(__builtin_isfinite(z0) && __builtin_isfinite(z1) && __builtin_isfinite(z2))) return drawn;
+  int c = 0;
+  float zc = z0;
+  if (z1 > zc) {
+    c = 1;
+    zc = z1;
+  }
+  if (z2 > zc) c = 2;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// First heuristic (Section 6.3).  LC: the learned-criterion variant (the
+// criterion scored by the network when criterion_rule is 1, and the features
+// of every contested placement dumped when asked).
+// ---------------------------------------------------------------------------
+template <typename K, bool LC>
+__global__ void __launch_bounds__(LC ? kH1LearnedMaxBlock : 1024) k_h1(BatchArgs a, int nbslots) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_caps[kMaxTypes];
   __shared__ int32_t s_scan[16];
@@ -259,7 +379,16 @@ __global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
   __shared__ int s_flag;
   const int tid = threadIdx.x, B = blockDim.x;
   constexpr int kArrays = sizeof(K) == 4 ? 1 : 2;
-  int32_t* lroom = reinterpret_cast<int32_t*>(smem);
+  H1Model* md = reinterpret_cast<H1Model*>(smem);
+  bool model_ok = true;
+  if constexpr (LC) {
+    if (a.criterion_rule == 1) {
+      stage_h1_model(a.model, md);
+      __syncthreads();
+      model_ok = md->n_out >= 3 && md->n_out <= kMaxTypes;
+    }
+  }
+  int32_t* lroom = reinterpret_cast<int32_t*>(smem + (LC ? kH1ModelBytes : 0));
   int32_t* lcap = lroom + (size_t)nbslots * B;
   int32_t* litem = lroom + (size_t)kArrays * nbslots * B;  // [s1][B]
   uint8_t* lloc = reinterpret_cast<uint8_t*>(litem + (size_t)a.s1 * B);  // [s1][B]
@@ -280,8 +409,9 @@ __global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
     const int c0 = a.cap_off[inst];
     const int n = a.cap_off[inst + 1] - c0;
     const int m = m64 > 0x7FFFFFFF ? 0x7FFFFFFF : (int)m64;
-    const int err = m64 > a.max_items ? kErrSize
-                                       : validate_block(a, inst, off, m, c0, n, s_caps, &s_flag);
+    int err = m64 > a.max_items ? kErrSize
+                                 : validate_block(a, inst, off, m, c0, n, s_caps, &s_flag);
+    if (!err && !model_ok) err = kErrModel;
     if (err) {
       if (tid == 0) {
         a.nbins[inst] = err;
@@ -295,6 +425,7 @@ __global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
     perm.init(seed, (uint32_t)m);
     const uint64_t ck = stream_key(seed, kStreamH1);
     const int s1 = a.s1;
+    const float inv_b1 = 1.0f / (float)s_caps[0];
     const int l = (m + s1 - 1) / s1;
     int32_t carry = 0;
     int64_t cost_acc = 0;
@@ -309,8 +440,39 @@ __global__ void __launch_bounds__(1024) k_h1(BatchArgs a, int nbslots) {
           const int q = q0 + t;
           const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
           const int32_t w = a.w[off + item];
-          const int crit = a.force_crit >= 0 ? a.force_crit : draw_criterion(ck, (uint64_t)q);
-          const int b = pk.place(w, crit, min(nbslots, n + 2 * t), s_caps, n, a.type_rule);
+          int crit = a.force_crit >= 0 ? a.force_crit : draw_criterion(ck, (uint64_t)q);
+          int b;
+          if constexpr (LC) {
+            int bff, bbf, bwf, nfit;
+            int32_t aff = 0, abf = 0, awf = 0;
+            pk.choices(w, min(nbslots, n + 2 * t), &bff, &bbf, &bwf, &nfit, &aff, &abf, &awf);
+            const bool contested = nfit > 0 && !(bff == bbf && bbf == bwf);
+            if (contested) {
+              float x[16];
+#pragma unroll
+              for (int i = 7; i < 16; ++i) x[i] = 0.0f;
+              x[0] = (float)w * inv_b1;
+              x[1] = (float)t * (1.0f / (float)k);
+              x[2] = (float)aff * inv_b1;
+              x[3] = (float)abf * inv_b1;
+              x[4] = (float)awf * inv_b1;
+              x[5] = (float)nfit * (1.0f / 16.0f);
+              x[6] = (float)pk.nb * (1.0f / 32.0f);
+              if (a.criterion_rule == 1) crit = h1_score(md, x, crit);
+              if (a.feat_out) {
+                float4* fo = reinterpret_cast<float4*>(a.feat_out + 16 * (off + q));
+                fo[0] = make_float4(x[0], x[1], x[2], x[3]);
+                fo[1] = make_float4(x[4], x[5], x[6], 0.0f);
+                fo[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                fo[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+              }
+            }
+            if (a.info_out) a.info_out[off + q] = contested ? 1 : 0;
+            b = pk.apply(nfit == 0 ? -1 : (crit == 0 ? bff : (crit == 1 ? bbf : bwf)), w,
+                         s_caps, n, a.type_rule);
+          } else {
+            b = pk.place(w, crit, min(nbslots, n + 2 * t), s_caps, n, a.type_rule);
+          }
           litem[t * B + tid] = item;
           lloc[t * B + tid] = (uint8_t)b;
         }
@@ -856,8 +1018,9 @@ __global__ void __launch_bounds__(1024) k_best_of(const int64_t* cost, int32_t n
 }  // namespace
 
 
-size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide) {
-  return (size_t)block * ((wide ? 2 : 1) * 4 * (size_t)nbslots + 4 * (size_t)s1 + (size_t)s1);
+size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide, bool learned) {
+  return (learned ? kH1ModelBytes : 0) +
+         (size_t)block * ((wide ? 2 : 1) * 4 * (size_t)nbslots + 4 * (size_t)s1 + (size_t)s1);
 }
 
 int h2_group(int s2) {
@@ -878,17 +1041,26 @@ size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k) {
 hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nbslots, int block, int grid,
                           hipStream_t s) {
   if (a.num <= 0) return hipSuccess;
-  const size_t lds = h1_lds_bytes(nbslots, a.s1, block, wide);
+  const bool lc = h1_learned(a);
+  const size_t lds = h1_lds_bytes(nbslots, a.s1, block, wide, lc);
   const int blocks = grid > 0 ? grid : a.num;
   hipError_t e;
-  if (!wide) {
-    { static bool done1 = false; e = raise_lds(k_h1<uint32_t>, lds, done1); }
+  if (!wide && !lc) {
+    { static bool done1 = false; e = raise_lds(k_h1<uint32_t, false>, lds, done1); }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h1<uint32_t>, dim3(blocks), dim3(block), lds, s, a, nbslots);
+    hipLaunchKernelGGL((k_h1<uint32_t, false>), dim3(blocks), dim3(block), lds, s, a, nbslots);
+  } else if (!lc) {
+    { static bool done2 = false; e = raise_lds(k_h1<uint64_t, false>, lds, done2); }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_h1<uint64_t, false>), dim3(blocks), dim3(block), lds, s, a, nbslots);
+  } else if (!wide) {
+    { static bool done3 = false; e = raise_lds(k_h1<uint32_t, true>, lds, done3); }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_h1<uint32_t, true>), dim3(blocks), dim3(block), lds, s, a, nbslots);
   } else {
-    { static bool done2 = false; e = raise_lds(k_h1<uint64_t>, lds, done2); }
+    { static bool done4 = false; e = raise_lds(k_h1<uint64_t, true>, lds, done4); }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h1<uint64_t>, dim3(blocks), dim3(block), lds, s, a, nbslots);
+    hipLaunchKernelGGL((k_h1<uint64_t, true>), dim3(blocks), dim3(block), lds, s, a, nbslots);
   }
   return hipGetLastError();
 }
@@ -928,8 +1100,10 @@ int occ(Kern kern, int block, size_t lds) {
 }
 }  // namespace
 
-int h1_blocks_per_cu(bool wide, int block, size_t lds) {
-  return wide ? occ(k_h1<uint64_t>, block, lds) : occ(k_h1<uint32_t>, block, lds);
+int h1_blocks_per_cu(bool wide, int block, size_t lds, bool learned) {
+  if (learned)
+    return wide ? occ(k_h1<uint64_t, true>, block, lds) : occ(k_h1<uint32_t, true>, block, lds);
+  return wide ? occ(k_h1<uint64_t, false>, block, lds) : occ(k_h1<uint32_t, false>, block, lds);
 }
 
 int h2_blocks_per_cu(H2Kernel k, int block, size_t lds) {

@@ -34,6 +34,7 @@ struct BatchArgs {
   int32_t force_crit;       // -1 or 0/1/2 (H1/H2 only)
   int32_t active_limit;     // plain FF/BF/WF: bins open at once (0: no limit)
   int32_t downsize;         // 1: a pass after packing gives every bin its smallest type
+  int32_t criterion_rule;   // H1: 0 Rule 3's draw, 1 the model picks FF/BF/WF
   int32_t s1;               // H1 items per sublist
   int32_t s2;               // H2 subset size
   int32_t slots;            // plain kernel: LDS key slots per wavefront
@@ -87,7 +88,16 @@ size_t plain_lds_block_extra(bool learned);
 inline bool plain_ext(const BatchArgs& a) {
   return a.src || a.force || a.feat_out || a.info_out || a.type_rule == 2;
 }
-size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide);
+// learned: the variant that scores the criterion (or dumps its features)
+size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide, bool learned = false);
+// H1 runs that take the criterion-scoring variant
+inline bool h1_learned(const BatchArgs& a) {
+  return a.criterion_rule == 1 || a.feat_out || a.info_out;
+}
+constexpr int32_t kErrModel = -9;
+// largest workgroup of the criterion-scoring H1 variant (its network needs
+// more than 128 registers per lane)
+constexpr int kH1LearnedMaxBlock = 512;
 // H2 kernels: one 32-bit key word per bin with a chunk of resolved positions
 // (the fast form), one packed 32-bit word per bin (when the fast form's LDS
 // does not fit), 64-bit bins (wide)
@@ -122,6 +132,12 @@ hipError_t launch_lpt_schedule(const int64_t* item_off, int32_t num, int32_t* sc
 // launch shapes; grid = 0 means one wavefront/workgroup per instance
 hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int waves_per_block,
                              size_t lds_per_wave, int grid, hipStream_t s);
+// plain FF/BF/WF with several instances per wavefront: `seg` lanes (16 or
+// 32) per instance, 32-bit keys, no scorer, hooks, bound or device region
+size_t plain_seg_stride(int slots, int max_items);
+hipError_t launch_plain_seg(const BatchArgs& a, int crit, int seg, int wpb, size_t seg_stride,
+                            int grid, hipStream_t s);
+int plain_seg_blocks_per_cu(int crit, int seg, int wpb, size_t seg_stride);
 hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
                           int grid, hipStream_t s);
 hipError_t launch_h2_grid(const BatchArgs& a, H2Kernel k, int nb_regs, int block_threads,
@@ -129,7 +145,7 @@ hipError_t launch_h2_grid(const BatchArgs& a, H2Kernel k, int nb_regs, int block
 // resident workgroups per CU for a launch shape (for persistent grids)
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int waves_per_block,
                         size_t lds_per_wave);
-int h1_blocks_per_cu(bool wide, int block_threads, size_t lds);
+int h1_blocks_per_cu(bool wide, int block_threads, size_t lds, bool learned = false);
 int h2_blocks_per_cu(H2Kernel k, int block_threads, size_t lds);
 
 }  // namespace vsbpp

@@ -81,9 +81,15 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     if (rc != VSBPP_OK) return rc;
   }
   if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
-  const bool ext = learned || (dec && (dec->src || dec->force || dec->features || dec->info));
-  if (ext && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
-  if (learned && !d_model) return VSBPP_E_MODEL;
+  const bool hooks = dec && (dec->src || dec->force || dec->features || dec->info);
+  if (heuristic == VSBPP_H1) {
+    // the first heuristic takes the learned criterion and the feature dump
+    // of its contested placements; nothing else here
+    if (learned || (dec && (dec->src || dec->force))) return VSBPP_E_OPTION;
+  } else if ((learned || hooks) && heuristic > VSBPP_WF) {
+    return VSBPP_E_OPTION;
+  }
+  if ((learned || o.criterion_rule == 1) && !d_model) return VSBPP_E_MODEL;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
   vsbpp::BatchArgs a{};
   a.w = b->weights;
@@ -105,6 +111,7 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
+  a.criterion_rule = o.criterion_rule;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   if (dec) {
@@ -113,7 +120,7 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     a.feat_out = dec->features;
     a.info_out = dec->info;
   }
-  a.model = o.type_rule == VSBPP_TYPE_LEARNED ? d_model : nullptr;
+  a.model = (o.type_rule == VSBPP_TYPE_LEARNED || o.criterion_rule == 1) ? d_model : nullptr;
   return vsbpp::enqueue_batch(a, heuristic, vsbpp::default_cfg(heuristic, a), nullptr, nullptr,
                               (hipStream_t)hip_stream);
 }

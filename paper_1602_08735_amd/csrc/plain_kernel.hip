@@ -138,11 +138,9 @@ __device__ int compact(K* keys, typename KeyT<K>::Pid* pid, int nlive, int32_t T
 
 // ---------------------------------------------------------------------------
 // Learned bin-type scorer, evaluated by one wavefront: lane l computes hidden
-// unit l of both hidden layers (bias, then an fp32 fused-multiply-add chain
-// over the inputs in index order, then ReLU).  The output layer runs on lanes
-// (k, g) = (lane >> 3, lane & 7): lane (k, g) forms the partial chain over
-// inputs 8g..8g+7 of output k, and lane k adds its bias and the eight
-// partials in order g = 0..7.
+// unit l of both hidden layers and lane k output k (each unit is its bias,
+// then an fp32 fused-multiply-add chain over its inputs in index order; the
+// hidden units then take ReLU).
 //
 // The model is staged once per workgroup at the start of LDS as fp32, laid
 // out so that lane l reads its rows of W1 and W2 as unit-stride 16-byte words
@@ -153,7 +151,7 @@ __device__ int compact(K* keys, typename KeyT<K>::Pid* pid, int nlive, int32_t T
 struct ModelLds {
   float w1[4 * 64 * 4];    // [i/4][l][4]
   float w2[16 * 64 * 4];   // [j/4][l][4]
-  float w3[16 * 8 * 8];    // [k][g][8]
+  float w3[16 * 16 * 4];   // [j/4][k][4]
   float b1[64], b2[64], b3[16];
   int32_t n_out;
 };
@@ -171,7 +169,10 @@ __device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
     const int l = e >> 6, j = e & 63;
     s->w2[(((j >> 2) * 64) + l) * 4 + (j & 3)] = bf16f(m->w2[e]);
   }
-  for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) s->w3[e] = bf16f(m->w3[e]);
+  for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+    const int k = e >> 6, j = e & 63;
+    s->w3[(((j >> 2) * 16) + k) * 4 + (j & 3)] = bf16f(m->w3[e]);
+  }
   for (int e = threadIdx.x; e < 64; e += blockDim.x) {
     s->b1[e] = m->b1[e];
     s->b2[e] = m->b2[e];
@@ -217,41 +218,30 @@ __device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], floa
     }
   }
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
-  float* part = hbuf + 64;
-  const int g = lane & 7;
+  // output k on lane k: weights of row k (unit stride over k for each four
+  // inputs) and the activations as broadcasts, four 16-byte words of each
+  // per LDS round trip
   float z = 0.0f;
-  for (int kb = 0; kb < md->n_out; kb += 8) {
-    const int k = kb + (lane >> 3);
-    const float4 w0 = *reinterpret_cast<const float4*>(&md->w3[(k * 8 + g) * 8]);
-    const float4 w1 = *reinterpret_cast<const float4*>(&md->w3[(k * 8 + g) * 8 + 4]);
-    const float4 h0 = *reinterpret_cast<const float4*>(&hbuf[g * 8]);
-    const float4 h1 = *reinterpret_cast<const float4*>(&hbuf[g * 8 + 4]);
-    float p = 0.0f;
-    p = __builtin_fmaf(w0.x, h0.x, p);
-    p = __builtin_fmaf(w0.y, h0.y, p);
-    p = __builtin_fmaf(w0.z, h0.z, p);
-    p = __builtin_fmaf(w0.w, h0.w, p);
-    p = __builtin_fmaf(w1.x, h1.x, p);
-    p = __builtin_fmaf(w1.y, h1.y, p);
-    p = __builtin_fmaf(w1.z, h1.z, p);
-    p = __builtin_fmaf(w1.w, h1.w, p);
-    part[lane] = p;
-    // lane kb + t (t < 8) folds the partials of output kb + t in order
-    const int t = lane - kb;
-    if (t >= 0 && t < 8) {
-      const float4 p0 = *reinterpret_cast<const float4*>(&part[t * 8]);
-      const float4 p1 = *reinterpret_cast<const float4*>(&part[t * 8 + 4]);
-      float a = md->b3[lane];
-      a = a + p0.x;
-      a = a + p0.y;
-      a = a + p0.z;
-      a = a + p0.w;
-      a = a + p1.x;
-      a = a + p1.y;
-      a = a + p1.z;
-      a = a + p1.w;
-      z = a;
+  if (lane < 16) {
+    const int k = lane;
+    float o = md->b3[k];
+#pragma unroll
+    for (int jo = 0; jo < 16; jo += 4) {
+      float4 wv[4], hv[4];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        wv[jb] = *reinterpret_cast<const float4*>(&md->w3[((jo + jb) * 16 + k) * 4]);
+        hv[jb] = *reinterpret_cast<const float4*>(&hbuf[(jo + jb) * 4]);
+      }
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        o = __builtin_fmaf(wv[jb].x, hv[jb].x, o);
+        o = __builtin_fmaf(wv[jb].y, hv[jb].y, o);
+        o = __builtin_fmaf(wv[jb].z, hv[jb].z, o);
+        o = __builtin_fmaf(wv[jb].w, hv[jb].w, o);
+      }
     }
+    z = o;
   }
   return z;
 }

@@ -48,7 +48,7 @@ int bucket(long long x) {
 
 std::string tune_key(int heuristic, const vsbpp::BatchArgs& a) {
   std::ostringstream k;
-  k << "h" << heuristic << (a.type_rule == 2 ? "L" : "") << "-m" << bucket(a.max_items)
+  k << "v2-h" << heuristic << (a.type_rule == 2 ? "L" : "") << (a.criterion_rule == 1 ? "C" : "") << "-m" << bucket(a.max_items)
     << "-t" << a.max_types << "-c"
     << (a.max_cap > 0x7FFF ? 1 : 0) << "-n" << bucket(a.num) << "-s"
     << (heuristic == VSBPP_H1 ? a.s1 : heuristic == VSBPP_H2 ? a.s2 : 0);
@@ -68,7 +68,7 @@ void load_cache_locked() {
   std::ifstream f(p);
   std::string key;
   vsbpp::LaunchCfg c;
-  while (f >> key >> c.mode >> c.lpt >> c.wpb >> c.block) g_tune[key] = c;
+  while (f >> key >> c.mode >> c.lpt >> c.wpb >> c.block >> c.seg) g_tune[key] = c;
 }
 
 void store_cache_locked() {
@@ -77,7 +77,7 @@ void store_cache_locked() {
   std::ofstream f(p, std::ios::trunc);
   for (const auto& kv : g_tune)
     f << kv.first << " " << kv.second.mode << " " << kv.second.lpt << " " << kv.second.wpb << " "
-      << kv.second.block << "\n";
+      << kv.second.block << " " << kv.second.seg << "\n";
 }
 
 int32_t run_eager(vsbpp_plan* p, hipStream_t s) {
@@ -153,7 +153,8 @@ int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
       // workgroups, which a stream of other launches dispatches faster)
       for (const auto& tc : timed)
         if (tc.first <= it->first * 1.02f && tc.second.mode == best->mode &&
-            tc.second.lpt == best->lpt && tc.second.wpb > best->wpb)
+            tc.second.lpt == best->lpt && tc.second.seg == best->seg &&
+            tc.second.wpb > best->wpb)
           *best = tc.second;
     }
   }
@@ -226,7 +227,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   int32_t rc = vsbpp::check_options_public(o);
   if (rc == VSBPP_OK) rc = vsbpp::check_heuristic_options_public(o, heuristic);
   if (rc != VSBPP_OK) return rc;
-  if (learned && !d_model) return VSBPP_E_MODEL;
+  if ((learned || o.criterion_rule == 1) && !d_model) return VSBPP_E_MODEL;
   if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
 
@@ -251,9 +252,10 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
+  a.criterion_rule = o.criterion_rule;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
-  a.model = learned ? d_model : nullptr;
+  a.model = (learned || o.criterion_rule == 1) ? d_model : nullptr;
   p->heuristic = heuristic;
 
   if (hipMalloc(&p->workspace, sizeof(int32_t) * ((size_t)a.num + 1)) != hipSuccess) {
@@ -277,6 +279,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
     p->cfg.lpt = launch->lpt;
     p->cfg.wpb = launch->waves_per_block;
     p->cfg.block = launch->block_threads;
+    p->cfg.seg = launch->lanes_per_instance == 0 ? 64 : launch->lanes_per_instance;
     rc = vsbpp::check_cfg(p->cfg, heuristic, a);
   } else {
     const std::string key = tune_key(heuristic, a);
@@ -331,6 +334,7 @@ int32_t vsbpp_plan_launch(const vsbpp_plan* p, vsbpp_launch* out) {
   out->lpt = p->cfg.lpt;
   out->waves_per_block = p->cfg.wpb;
   out->block_threads = p->cfg.block;
+  out->lanes_per_instance = p->cfg.seg;
   return VSBPP_OK;
 }
 

@@ -56,12 +56,15 @@ int32_t check_options(const vsbpp_options& o) {
   if (o.force_criterion < -1 || o.force_criterion > VSBPP_WF) return VSBPP_E_OPTION;
   if (o.active_limit < 0) return VSBPP_E_OPTION;
   if (o.downsize != 0 && o.downsize != 1) return VSBPP_E_OPTION;
+  if (o.criterion_rule != 0 && o.criterion_rule != 1) return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
 
 // options that only some heuristics take
 int32_t check_heuristic_options(const vsbpp_options& o, int32_t heuristic) {
   if (o.active_limit > 0 && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
+  if (o.criterion_rule == 1 && (heuristic != VSBPP_H1 || o.force_criterion != -1))
+    return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
 
@@ -164,7 +167,7 @@ H2Kernel h2_kernel(const BatchArgs& a, int block) {
 size_t h_lds(int heuristic, const BatchArgs& a, int block) {
   const bool wide = is_wide(a);
   const int nbs = h_nbslots(heuristic, a);
-  return heuristic == VSBPP_H1 ? h1_lds_bytes(nbs, a.s1, block, wide)
+  return heuristic == VSBPP_H1 ? h1_lds_bytes(nbs, a.s1, block, wide, h1_learned(a))
                                : h2_lds_bytes(nbs, block, h2_group(a.s2), h2_kernel(a, block));
 }
 
@@ -173,20 +176,53 @@ int h_fit_block(int heuristic, const BatchArgs& a, int want) {
   const int gran = heuristic == VSBPP_H2 ? h2_group(a.s2) : 64;
   int b = want < gran ? gran : (want / gran) * gran;
   if (b > 1024) b = (1024 / gran) * gran;
+  if (heuristic == VSBPP_H1 && h1_learned(a) && b > kH1LearnedMaxBlock) b = kH1LearnedMaxBlock;
   const size_t budget = (size_t)(device_info().max_lds_block - kStaticLdsReserve);
   while (b > gran && h_lds(heuristic, a, b) > budget) b -= gran;
   if (h_lds(heuristic, a, b) > budget) return 0;
   return b;
 }
 
+// LDS layout of the several-instances-per-wavefront kernel: bytes per
+// segment, and the most wavefronts per workgroup (at most 4) that fit; 0 when
+// not even one fits
+struct SegShape {
+  int slots;
+  size_t stride;
+  int max_wpb;
+};
+
+SegShape seg_shape(const BatchArgs& a, int seg) {
+  SegShape sh;
+  sh.slots = round_up(a.max_items, 4 * seg);
+  sh.stride = plain_seg_stride(sh.slots, a.max_items);
+  const size_t per_wave = sh.stride * (size_t)(64 / seg);
+  const size_t fit = (size_t)device_info().max_lds_block / per_wave;
+  sh.max_wpb = fit > 4 ? 4 : (int)fit;
+  return sh;
+}
+
 }  // namespace
+
+bool seg_eligible(const BatchArgs& a, int heuristic) {
+  return heuristic <= VSBPP_WF && !is_wide(a) && !plain_ext(a) && a.active_limit == 0 &&
+         a.max_items >= 1 && (seg_shape(a, 16).max_wpb >= 1 || seg_shape(a, 32).max_wpb >= 1);
+}
 
 int32_t check_cfg(const LaunchCfg& c, int heuristic, const BatchArgs& a) {
   if (c.mode < 0 || c.mode > 1 || c.lpt < 0 || c.lpt > 1) return VSBPP_E_OPTION;
   if (c.lpt && a.num > kLptMax) return VSBPP_E_OPTION;
+  if (c.seg != 64 && c.seg != 32 && c.seg != 16) return VSBPP_E_OPTION;
   if (heuristic <= VSBPP_WF) {
     if (c.wpb < 1 || c.wpb > 8) return VSBPP_E_OPTION;
+    if (c.seg != 64) {
+      if (c.wpb > 4 || !seg_eligible(a, heuristic) || seg_shape(a, c.seg).max_wpb < 1)
+        return VSBPP_E_OPTION;
+    }
   } else {
+    if (c.seg != 64) return VSBPP_E_OPTION;
+    if (heuristic == VSBPP_H1 && h1_learned(a) && c.block > kH1LearnedMaxBlock)
+      return VSBPP_E_OPTION;
     if (c.block < 64 || c.block > 1024 || (c.block & 63)) return VSBPP_E_OPTION;
     if (heuristic == VSBPP_H2 && (c.block % h2_group(a.s2))) return VSBPP_E_OPTION;
   }
@@ -219,6 +255,20 @@ std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a) {
           c.wpb = wpb;
           v.push_back(c);
         }
+        if (seg_eligible(a, heuristic)) {
+          for (int seg : {16, 32}) {
+            const int mw = seg_shape(a, seg).max_wpb;  // 0: this width does not fit
+            for (int wpb : {1, 2, 4}) {
+              if (wpb > mw) continue;
+              LaunchCfg c;
+              c.mode = mode;
+              c.lpt = lpt;
+              c.wpb = wpb;
+              c.seg = seg;
+              v.push_back(c);
+            }
+          }
+        }
       } else {
         const int gran = heuristic == VSBPP_H2 ? h2_group(a.s2) : 64;
         for (int b = gran; b <= 1024; b *= 2) {
@@ -249,6 +299,48 @@ int64_t plain_spill_bytes(const BatchArgs& a, int heuristic) {
   return sh.spill ? (int64_t)sh.per_wave * (int64_t)a.num : 0;
 }
 
+BatchArgs batch_args(const vsbpp_batch& b, const vsbpp_options& o) {
+  BatchArgs a{};
+  a.w = b.weights;
+  a.item_off = b.item_off;
+  a.caps = b.capacities;
+  a.cap_off = b.cap_off;
+  a.order = b.order;
+  a.seeds = b.seeds;
+  a.seed = o.seed;
+  a.assign = b.assignment;
+  a.types = b.bin_types;
+  a.nbins = b.nbins;
+  a.cost = b.cost;
+  a.num = b.num_instances;
+  a.max_items = b.max_items;
+  a.max_cap = b.max_capacity;
+  a.max_types = b.max_types;
+  a.type_rule = o.type_rule;
+  a.force_crit = o.force_criterion;
+  a.active_limit = o.active_limit;
+  a.downsize = o.downsize;
+  a.criterion_rule = o.criterion_rule;
+  a.s1 = o.h1_items_per_sublist;
+  a.s2 = o.h2_subset_size;
+  return a;
+}
+
+int32_t check_batch(const vsbpp_batch* b, int32_t heuristic, const vsbpp_options& o) {
+  if (!b) return VSBPP_E_NULL;
+  if (b->num_instances < 0) return VSBPP_E_SIZE;
+  if (b->num_instances > 0 &&
+      (!b->weights || !b->item_off || !b->capacities || !b->cap_off || !b->assignment ||
+       !b->bin_types || !b->nbins || !b->cost))
+    return VSBPP_E_NULL;
+  if (b->max_items < 1 || b->max_types < 1 || b->max_types > kMaxTypes || b->max_capacity < 1)
+    return VSBPP_E_SIZE;
+  if (heuristic < VSBPP_FF || heuristic > VSBPP_H2) return VSBPP_E_HEURISTIC;
+  int32_t rc = check_options(o);
+  if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
+  return rc;
+}
+
 int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* queue,
                       int32_t* sched, hipStream_t s) {
   if (a.num <= 0) return VSBPP_OK;
@@ -268,7 +360,18 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     if (e != hipSuccess) goto fail;
     a.queue = queue;
   }
-  if (heuristic <= VSBPP_WF) {
+  if (heuristic <= VSBPP_WF && c.seg != 64) {
+    // several instances per wavefront
+    if (!seg_eligible(a, heuristic)) return VSBPP_E_OPTION;
+    const SegShape sh = seg_shape(a, c.seg);
+    if (sh.max_wpb < 1) return VSBPP_E_OPTION;
+    a.spill = nullptr;
+    a.slots = sh.slots;
+    const int wpb = c.wpb < sh.max_wpb ? c.wpb : sh.max_wpb;
+    int grid = 0;
+    if (c.mode == 1) grid = d.cus * plain_seg_blocks_per_cu(heuristic, c.seg, wpb, sh.stride);
+    e = launch_plain_seg(a, heuristic, c.seg, wpb, sh.stride, grid, s);
+  } else if (heuristic <= VSBPP_WF) {
     PlainShape sh;
     int32_t rc = plain_shape(a, &sh);
     if (rc != VSBPP_OK) return rc;
@@ -288,7 +391,7 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     int grid = 0;
     if (c.mode == 1) {
       const size_t lds = h_lds(heuristic, a, block);
-      grid = d.cus * (heuristic == VSBPP_H1 ? h1_blocks_per_cu(wide, block, lds)
+      grid = d.cus * (heuristic == VSBPP_H1 ? h1_blocks_per_cu(wide, block, lds, h1_learned(a))
                                             : h2_blocks_per_cu(h2_kernel(a, block), block, lds));
     }
     e = heuristic == VSBPP_H1 ? launch_h1_grid(a, wide, nbs, block, grid, s)
@@ -348,6 +451,7 @@ void vsbpp_options_init(vsbpp_options* opt) {
   opt->order = nullptr;
   opt->active_limit = 0;
   opt->downsize = 0;
+  opt->criterion_rule = 0;
 }
 
 const char* vsbpp_strerror(int32_t code) {
@@ -383,6 +487,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   rc = check_options(o);
   if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
   if (rc != VSBPP_OK) return rc;
+  if (o.criterion_rule == 1) return VSBPP_E_MODEL;  // this call takes no model
 
   std::lock_guard<std::mutex> lk(g_mu);
   if (!device_ok_locked()) return VSBPP_E_DEVICE;
@@ -482,6 +587,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
   int32_t rc = check_options(o);
   if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
   if (rc != VSBPP_OK) return rc;
+  if (o.criterion_rule == 1) return VSBPP_E_MODEL;  // this call takes no model
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!device_ok_locked()) return VSBPP_E_DEVICE;

@@ -16,11 +16,24 @@ def test_cpu_baseline_runs_every_launch():
     assert all(0 < v <= 1 for v in scored.values())
 
 
-def test_work_per_item_counts_the_network():
-    for h in bench.LEARNED:
-        assert bench.ops_per_item(h) > bench.ops_per_bin_test(h) * bench.BIN_TESTS_PER_ITEM[h]
-    assert bench.ops_per_item("BF") == 2 * bench.BIN_TESTS_PER_ITEM["BF"]
-    # the P-system packers: compare, select and key per bin of the packer
-    assert bench.ops_per_item("H2") == 3 * bench.BIN_TESTS_PER_ITEM["H2"]
-    assert bench.lds_bytes_per_item("H2") is None
-    assert bench.lds_bytes_per_item("BF") == 2 * bench.BIN_TESTS_PER_ITEM["BF"] + 2
+def test_kernel_roofline_work_and_bound():
+    """Work per launch of every resource and the bound: the scorer runs count
+    the network's FLOP, the plain runs LDS bytes and integer ops, the
+    P-system packers integer ops only; frac = work / time / peak."""
+    items = 1000
+    tests, scored = bench.BIN_TESTS_PER_ITEM, bench.SCORED_DECISIONS_PER_ITEM
+    r = bench.kernel_roofline("BF", 2.0, items, tests, scored, None)
+    assert r["work"]["int_valu"] == 2 * tests["BF"] * items
+    assert r["work"]["lds"] == (2 * tests["BF"] + 2) * items
+    assert "fp32_fma" not in r["work"]
+    assert abs(r["lds_frac"] - r["work"]["lds"] / 2e-3 / bench.LDS_PEAK) < 1e-12
+    h2 = bench.kernel_roofline("H2", 1.0, items, tests, scored, None)
+    assert h2["work"] == {"int_valu": 3 * tests["H2"] * items} and h2["bound"] == "int_valu"
+    w = bench.kernel_roofline("WF+scorer", 1.0, items, tests, scored,
+                              {"lds_bytes_per_s": 5e13, "valu_int32_ops_per_s": 3e13})
+    assert w["work"]["fp32_fma"] == 2 * bench.MLP_FMA_PER_DECISION * scored["WF+scorer"] * items
+    assert w["bound"] == "fp32_fma"
+    assert abs(w["lds_frac_of_achievable"] - w["work"]["lds"] / 1e-3 / 5e13) < 1e-12
+    ro = bench.roofline_object("WF+scorer", w, items, tests, scored)
+    assert ro["bound"] == "alu" and ro["unit"] == "TFLOP/s"
+    assert abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-12

@@ -47,6 +47,8 @@ def _launches(h):
         for lpt in (0, 1):
             if h in ("FF", "BF", "WF"):
                 out += [dict(mode=mode, lpt=lpt, waves_per_block=w) for w in (1, 2, 4, 8)]
+                out += [dict(mode=mode, lpt=lpt, waves_per_block=w, lanes_per_instance=s)
+                        for s in (16, 32) for w in (1, 4)]
             elif h == "H1":
                 out += [dict(mode=mode, lpt=lpt, block_threads=b) for b in (64, 256, 1024)]
             else:

@@ -220,3 +220,193 @@ def test_training_gradient_finite_differences():
         fd = (mlp_train.loss_only(flat + e, n_out, X, mask, label)
               - mlp_train.loss_only(flat - e, n_out, X, mask, label)) / (2 * h)
         assert abs(fd - g[p]) <= 1e-6 + 1e-5 * abs(fd), (p, fd, g[p])
+
+
+def test_output_unit_is_one_index_order_chain(orc):
+    """An output score is its bias followed by one fp32 fused multiply-add
+    chain over h2 in index order.  With h2 = 1 everywhere and output weights
+    2^24, 1 at inputs 0, 1 and 1, -2^24 at inputs 8, 9, that chain loses both
+    ones to rounding (2^24 + 1 rounds to even) and ends at exactly 0; summing
+    groups of inputs separately, or in float64, gives 1 or 2."""
+    w3 = np.zeros((3, 64))
+    w3[0, [0, 1, 8, 9]] = [2.0**24, 1.0, 1.0, -(2.0**24)]
+    w3[1, 5] = 1.0
+    mdl = orc.make_model(np.zeros((64, 16)), np.zeros(64), np.zeros((64, 64)), np.ones(64),
+                         w3, np.zeros(3))
+    z = orc.mlp_forward(mdl, np.zeros(16, np.float32))
+    assert z.tolist() == [0.0, 1.0, 0.0]
+    assert f64_forward(orc, mdl, np.zeros(16))[0] == 2.0
+
+
+def test_hidden_unit_is_one_index_order_chain(orc):
+    """The same rounding argument for a hidden unit of the second layer:
+    h1 = 1 (from bias), weights 2^24, 1, 1, -2^24 at inputs 0, 1, 2, 3 give
+    exactly 0 after ReLU's pass-through, so an output reading it sees 0."""
+    w2 = np.zeros((64, 64))
+    w2[0, :4] = [2.0**24, 1.0, 1.0, -(2.0**24)]
+    w3 = np.zeros((3, 64))
+    w3[0, 0] = 1.0
+    w3[2, 0] = -1.0
+    mdl = orc.make_model(np.zeros((64, 16)), np.ones(64), w2, np.zeros(64), w3,
+                         np.array([0.0, 0.5, 0.0]))
+    z = orc.mlp_forward(mdl, np.zeros(16, np.float32))
+    assert z.tolist() == [0.0, 0.5, 0.0]
+
+
+# ---------------------------------------------------------------------------
+# The learned criterion of the first heuristic
+# ---------------------------------------------------------------------------
+def _h1_replay(w, caps, order, s1, crit_of):
+    """Plain-Python first heuristic over an explicit order (Section 6.3):
+    sublists of s1 consecutive positions, Rule-2 bins of every type, the
+    criterion of position q from crit_of(q, bins, w) (bins = list of
+    [capacity, load, divided]), FF/BF/WF with lowest-index ties, smallest
+    fitting type for a new bin, Rule 5 once per bin.  Returns the assignment
+    in canonical ids and the list of (q, features) of contested placements."""
+    caps = [int(c) for c in caps]
+    m = len(w)
+    assign = [0] * m
+    base = 0
+    feats = []
+    for q0 in range(0, m, s1):
+        k = min(s1, m - q0)
+        bins = [[c, 0, False] for c in caps]
+        local = []
+        for t in range(k):
+            q = q0 + t
+            wj = int(w[order[q]])
+            fit = [b for b, (c, ld, _) in enumerate(bins) if c - ld >= wj]
+            c_used, f = crit_of(q, t, k, bins, wj, fit)
+            if f is not None:
+                feats.append((q, f))
+            if not fit:
+                ty = max(i for i in range(len(caps)) if caps[i] >= wj)
+                bins.append([caps[ty], 0, False])
+                b = len(bins) - 1
+            else:
+                after = {b: bins[b][0] - bins[b][1] - wj for b in fit}
+                if c_used == 0:
+                    b = fit[0]
+                elif c_used == 1:
+                    b = min(fit, key=lambda i: (after[i], i))
+                else:
+                    b = min(fit, key=lambda i: (-after[i], i))
+            bins[b][1] += wj
+            if not bins[b][2] and 2 * bins[b][1] >= bins[b][0]:
+                bins[b][2] = True
+                bins.append([bins[b][0], 0, False])
+            local.append(b)
+        used = [b for b in range(len(bins)) if bins[b][1] > 0]
+        rank = {b: i for i, b in enumerate(used)}
+        for t in range(k):
+            assign[order[q0 + t]] = base + rank[local[t]]
+        base += len(used)
+    return np.array(assign), feats
+
+
+def _h1_features(t, k, bins, wj, fit, b1):
+    """Features of a contested placement, recomputed in numpy float32."""
+    f32 = np.float32
+    after = [bins[b][0] - bins[b][1] - wj for b in fit]
+    ff = fit[0]
+    bf = min(fit, key=lambda i: (bins[i][0] - bins[i][1] - wj, i))
+    wf = min(fit, key=lambda i: (-(bins[i][0] - bins[i][1] - wj), i))
+    if ff == bf == wf:
+        return None, None
+    inv = f32(1.0) / f32(b1)
+    x = np.zeros(16, np.float32)
+    x[0] = f32(wj) * inv
+    x[1] = f32(t) * (f32(1.0) / f32(k))
+    x[2] = f32(bins[ff][0] - bins[ff][1] - wj) * inv
+    x[3] = f32(min(after)) * inv
+    x[4] = f32(max(after)) * inv
+    x[5] = f32(len(fit)) * f32(1.0 / 16.0)
+    x[6] = f32(len(bins)) * f32(1.0 / 32.0)
+    return x, (ff, bf, wf)
+
+
+def test_h1_learned_criterion_replay(orc):
+    """Every contested placement of the learned first heuristic: its features
+    recomputed from the packer state in plain Python, its criterion the
+    network's argmax over FF/BF/WF, and the whole packing reproduced by a
+    plain-Python first heuristic that follows those criteria (the draw of
+    Rule 3 elsewhere)."""
+    rng = np.random.default_rng(41)
+    for trial in range(12):
+        mdl = random_model(orc, rng, n_out=3 + trial % 3)
+        n = int(rng.integers(1, 6))
+        caps = np.sort(rng.choice(np.arange(10, 300), n, replace=False))[::-1]
+        m = int(rng.integers(1, 90))
+        w = rng.integers(1, caps[0] + 1, m)
+        order = rng.permutation(m)
+        seed = int(rng.integers(0, 2**40))
+        r = orc.pack(w, caps, "H1", seed=seed, order=order, model=mdl, criterion_rule=1,
+                     trace=True)
+        dec = {d.position: d for d in r.stats["decisions"]}
+        key = orc.stream_key(seed, 2)
+
+        def crit_of(q, t, k, bins, wj, fit):
+            drawn = orc.criterion(key, q)
+            if not fit:
+                assert q not in dec
+                return drawn, None
+            x, _ = _h1_features(t, k, bins, wj, fit, caps[0])
+            if x is None:
+                assert q not in dec
+                return drawn, None
+            d = dec[q]
+            assert d.weight == wj and d.plain_type == drawn
+            assert np.array_equal(np.array(d.feat, np.float32), x), (trial, q)
+            z = orc.mlp_forward(mdl, x)[:3]
+            assert d.chosen == int(np.argmax(z)), (trial, q)
+            return d.chosen, x
+
+        a, feats = _h1_replay(w, caps, order, 10, crit_of)
+        assert len(feats) == len(dec)
+        assert np.array_equal(a, r.assignment), trial
+
+
+@pytest.mark.parametrize("c", [0, 1, 2])
+def test_h1_constant_scorer_is_the_forced_criterion(orc, c):
+    """A network whose scores are constant with criterion c on top gives the
+    forced-c run exactly: where the three criteria agree or nothing fits, the
+    criterion does not change the placement."""
+    rng = np.random.default_rng(50 + c)
+    b3 = np.zeros(3)
+    b3[c] = 1.0
+    mdl = orc.make_model(np.zeros((64, 16)), np.zeros(64), np.zeros((64, 64)), np.zeros(64),
+                         np.zeros((3, 64)), b3)
+    for _ in range(20):
+        w, caps = inputs.c2_instance(rng, int(rng.integers(1, 400)))
+        seed = int(rng.integers(0, 2**40))
+        a = orc.pack(w, caps, "H1", seed=seed, model=mdl, criterion_rule=1)
+        b = orc.pack(w, caps, "H1", seed=seed, force_crit=c)
+        assert a.cost == b.cost and np.array_equal(a.assignment, b.assignment)
+        assert np.array_equal(a.bin_types, b.bin_types)
+
+
+def test_h1_non_finite_scores_keep_the_draw(orc):
+    rng = np.random.default_rng(60)
+    b3 = np.array([0.0, np.nan, 0.0])
+    mdl = orc.make_model(np.zeros((64, 16)), np.zeros(64), np.zeros((64, 64)), np.zeros(64),
+                         np.zeros((3, 64)), b3)
+    for _ in range(10):
+        w, caps = inputs.c2_instance(rng, int(rng.integers(1, 300)))
+        a = orc.pack(w, caps, "H1", seed=9, model=mdl, criterion_rule=1)
+        b = orc.pack(w, caps, "H1", seed=9)
+        assert a.cost == b.cost and np.array_equal(a.assignment, b.assignment)
+
+
+def test_h1_learned_criterion_option_checks(orc):
+    rng = np.random.default_rng(61)
+    mdl = random_model(orc, rng, n_out=3)
+    small = random_model(orc, rng, n_out=2)
+    w, caps = [3, 4, 5], [10, 7]
+    for h, kw in (("H2", dict(model=mdl)), ("BF", dict(model=mdl)),
+                  ("H1", dict(model=mdl, force_crit=1)), ("H1", dict(model=small)),
+                  ("H1", dict())):
+        with pytest.raises(orc.OracleError) as e:
+            orc.pack(w, caps, h, criterion_rule=1, **kw)
+        assert e.value.code == -6, (h, kw)
+    with pytest.raises(orc.OracleError):
+        orc.pack(w, caps, "H1", criterion_rule=2, model=mdl)
