@@ -83,6 +83,7 @@ class _Opts(ctypes.Structure):
         ("active_limit", ctypes.c_int32),
         ("downsize", ctypes.c_int32),
         ("criterion_rule", ctypes.c_int32),
+        ("choice_rule", ctypes.c_int32),
     ]
 
 
@@ -140,6 +141,9 @@ def lib():
         L.orc_rollout_label_ex.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, i64p]
+        L.orc_choice_label.restype = ctypes.c_int32
+        L.orc_choice_label.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, i64p]
         L.orc_lb_sum.restype = ctypes.c_int64
         L.orc_lb_sum.argtypes = [i32p, ctypes.c_int32]
         _lib = L
@@ -196,7 +200,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
          type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
          order=None, model: "Model | None" = None, force_event: int = -1,
          force_types=(0, 0), trace: bool = False, active_limit: int = 0,
-         downsize: bool = False, criterion_rule: int = 0) -> Packing:
+         downsize: bool = False, criterion_rule: int = 0, choice_rule: int = 0) -> Packing:
     w = _i32(weights)
     c = _i32(caps)
     m = int(w.size)
@@ -212,6 +216,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     o.active_limit = int(active_limit)
     o.downsize = int(downsize)
     o.criterion_rule = int(criterion_rule)
+    o.choice_rule = int(choice_rule)
     tr_arr = None
     tr_count = ctypes.c_int32(0)
     if trace:
@@ -330,4 +335,15 @@ def rollout_label(weights, caps, crit: int, d: int, *, type_rule: int = TYPE_SMA
     lab = lib().orc_rollout_label_ex(_p32(w), int(w.size), _p32(c), int(c.size), crit, d,
                                      int(type_rule), int(downsize),
                                      vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return int(lab), vals
+
+
+def choice_label(weights, caps, crit: int, d: int):
+    """(label, values) of contested placement d of a plain run under the
+    largest type rule with downsizing (depth-2 lookahead over {the criterion's
+    bin, a new bin})."""
+    w, c = _i32(weights), _i32(caps)
+    vals = np.zeros(2, dtype=np.int64)
+    lab = lib().orc_choice_label(_p32(w), int(w.size), _p32(c), int(c.size), crit, d,
+                                 vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return int(lab), vals

@@ -143,10 +143,14 @@ static int32_t open_type(const int32_t* caps, int32_t n, int32_t w, int32_t rule
  * `suffix_min` is the smallest weight among this item and all later items of
  * the same packer; it only feeds the work counters. */
 typedef int32_t (*type_chooser)(void* ctx, int32_t w);
+/* plain runs under a choice rule: given the criterion's bin, 1 opens a new
+ * bin instead */
+typedef int32_t (*bin_chooser)(void* ctx, const obin* b, int32_t w);
 
 static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
                      int32_t crit, int32_t rule5, int32_t type_rule, int32_t active_limit,
-                     int64_t suffix_min, orc_stats* st, type_chooser choose, void* cctx) {
+                     int64_t suffix_min, orc_stats* st, type_chooser choose, void* cctx,
+                     bin_chooser choose_bin) {
   int32_t best = -1;
   int64_t best_after = 0;
   for (int32_t b = 0; b < p->nb; ++b) {
@@ -167,6 +171,7 @@ static int32_t place(opacker* p, const int32_t* caps, int32_t n, int32_t w,
       best_after = after;
     }
   }
+  if (best >= 0 && choose_bin && choose_bin(cctx, &p->b[best], w)) best = -1;
   if (best < 0) {
     if (active_limit > 0) {
       int32_t open = 0, fullest = -1;
@@ -256,6 +261,14 @@ static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_
     if (o->active_limit < 0 || (o->active_limit > 0 && heuristic > ORC_WF)) return ORC_E_OPTION;
     if (o->downsize != 0 && o->downsize != 1) return ORC_E_OPTION;
     if (o->criterion_rule != 0 && o->criterion_rule != 1) return ORC_E_OPTION;
+    if (o->choice_rule < 0 || o->choice_rule > 2) return ORC_E_OPTION;
+    if (o->choice_rule > 0 &&
+        (heuristic > ORC_WF || o->type_rule != ORC_TYPE_LARGEST || o->downsize != 1 ||
+         o->active_limit != 0))
+      return ORC_E_OPTION;
+    if (o->choice_rule == 2 &&
+        (!o->model || o->model->n_out < 2 || o->model->n_out > ORC_MAX_OUT))
+      return ORC_E_OPTION;
     if (o->criterion_rule == 1 &&
         (heuristic != ORC_H1 || o->force_crit != -1 || !o->model || o->model->n_out < 3 ||
          o->model->n_out > ORC_MAX_OUT))
@@ -409,6 +422,77 @@ static int32_t plain_choose(void* vc, int32_t w) {
   return chosen;
 }
 
+/* Learned bin choice (plain FF/BF/WF under the largest type rule with
+ * downsizing).  Section 1 leaves open how bins and their types are chosen
+ * beyond the three rules; with downsizing a bin of load L costs c(L), the
+ * smallest capacity >= L, whatever type it was opened with.  A placement of
+ * w into the criterion's bin (load L) is contested when c(L + w) > c(L):
+ * the bin becomes costlier.  At a contested placement the alternative is a
+ * new bin (of type B_1, the largest type rule's).  The scores decide: output
+ * 1 (new bin) must be strictly larger than output 0 (the criterion's bin)
+ * and both finite; elsewhere, and on ties, the criterion's bin is kept. */
+static int64_t holding_cap(const int32_t* caps, int32_t n, int64_t load) {
+  int64_t c = caps[0];
+  for (int32_t k = 0; k < n; ++k)
+    if (caps[k] >= load) c = caps[k];
+  return c;
+}
+
+/* The 16 features of a contested placement (fp32; "* (1/a)" multiplies by
+ * the fp32 reciprocal 1.0f/a): 0..10 as for a type decision (item, the items
+ * after it, bins so far and their room histogram), then, for the criterion's
+ * bin b with load L and capacity C:
+ *  11 (C - L - w) * (1/B_1)          room left in b after the item
+ *  12 (c(L + w) - c(L)) * (1/B_1)    what placing the item in b adds
+ *  13 c(w) * (1/B_1)                 the cost of a new bin holding the item
+ *  14 (c(L + w) - L - w) * (1/B_1)   b's slack after the item
+ *  15 (c(L) - L) * (1/B_1)           b's slack before it */
+static void choice_features(const plain_ctx* c, const obin* b, float* x) {
+  decision_features(c, x);
+  const float inv_b1 = 1.0f / (float)c->caps[0];
+  const int64_t L = b->load, w = c->w;
+  const int64_t before = holding_cap(c->caps, c->n, L);
+  const int64_t after = holding_cap(c->caps, c->n, L + w);
+  x[11] = (float)((int64_t)c->caps[b->type] - L - w) * inv_b1;
+  x[12] = (float)(after - before) * inv_b1;
+  x[13] = (float)holding_cap(c->caps, c->n, w) * inv_b1;
+  x[14] = (float)(after - L - w) * inv_b1;
+  x[15] = (float)(before - L) * inv_b1;
+}
+
+static int32_t plain_choice(void* vc, const obin* b, int32_t w) {
+  plain_ctx* c = (plain_ctx*)vc;
+  const orc_opts* o = c->o;
+  if (holding_cap(c->caps, c->n, b->load + w) == holding_cap(c->caps, c->n, b->load))
+    return 0; /* not contested */
+  const int32_t d = c->event++;
+  int32_t open = 0;
+  float x[ORC_NFEAT];
+  const int need_feat = o->choice_rule == 2 || (o->trace && d < o->trace_cap);
+  if (need_feat) choice_features(c, b, x);
+  if (o->choice_rule == 2) {
+    float z[ORC_MAX_OUT];
+    orc_mlp_forward(o->model, x, z);
+    open = (isfinite(z[0]) && isfinite(z[1]) && z[1] > z[0]) ? 1 : 0;
+  }
+  if (o->force_event >= 0) {
+    int32_t t = -1;
+    if (d == o->force_event) t = o->force_t1;
+    else if (d == o->force_event + 1) t = o->force_t2;
+    if (t == 0 || t == 1) open = t;
+  }
+  if (o->trace && d < o->trace_cap) {
+    orc_decision* r = &o->trace[d];
+    r->position = c->q;
+    r->weight = w;
+    r->plain_type = 0;
+    r->chosen = open;
+    r->feasible = 3u;
+    memcpy(r->feat, x, sizeof x);
+  }
+  return open;
+}
+
 /* Plain FF/BF/WF (Section 1): one packer over the whole list, starting with
  * no bins, one fixed criterion, no Rule 2 and no Rule 5.  The type of a bin
  * opened when nothing fits follows the type rule, the scorer, or a forced
@@ -441,7 +525,8 @@ static int32_t run_plain(const int32_t* w, int32_t m, const int32_t* caps, int32
     c.nb = p.nb;
     const int32_t nb_before = p.nb;
     const int32_t b = place(&p, caps, n, wq, crit, 0, o->type_rule, o->active_limit, smin[q], st,
-                              plain_choose, &c);
+                            o->choice_rule ? NULL : plain_choose, &c,
+                            o->choice_rule ? plain_choice : NULL);
     local[q] = b;
     const int64_t room = (int64_t)caps[p.b[b].type] - p.b[b].load;
     if (b != nb_before) c.hist[room_bucket(room + wq, caps[0])]--;
@@ -475,7 +560,7 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
   orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize, 0};
+  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize, 0, 0};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label = -1;
   if (rc >= 0 && d < count) {
@@ -487,7 +572,7 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
       if (!((feasible >> k1) & 1u)) continue;
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < n; ++k2) {
-        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize, 0};
+        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize, 0, 0};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }
@@ -506,6 +591,36 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
   free(assign);
   free(types);
   free(tr);
+  return label;
+}
+
+int32_t orc_choice_label(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                         int32_t crit, int32_t d, int64_t* values) {
+  if (!w || !caps || !values) return ORC_E_NULL;
+  if (crit < ORC_FF || crit > ORC_WF || d < 0) return ORC_E_OPTION;
+  int32_t* assign = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int32_t* types = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int32_t count = 0;
+  int64_t cost = 0;
+  orc_opts o = {0, 10, 5, ORC_TYPE_LARGEST, -1, NULL, NULL, -1, 0, 0, NULL, 0, &count, 0, 1, 0, 1};
+  int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
+  int32_t label;
+  if (rc >= 0 && d < count) {
+    for (int32_t k1 = 0; k1 < 2; ++k1) {
+      int64_t v = -1;
+      for (int32_t k2 = 0; k2 < 2; ++k2) {
+        orc_opts f = {0, 10, 5, ORC_TYPE_LARGEST, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, 1, 0, 1};
+        orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
+        if (v < 0 || cost < v) v = cost;
+      }
+      values[k1] = v;
+    }
+    label = values[1] < values[0] ? 1 : 0;
+  } else {
+    label = rc >= 0 ? ORC_E_OPTION : rc;
+  }
+  free(assign);
+  free(types);
   return label;
 }
 
@@ -600,7 +715,8 @@ static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
                                      : orc_criterion(ck, (uint64_t)(q0 + t));
       if (o->criterion_rule == 1)
         c = h1_learned_criterion(&p, caps, w[items[t]], t, k, q0 + t, c, o);
-      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL);
+      local[t] = place(&p, caps, n, w[items[t]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL,
+                       NULL);
     }
     base += emit_packer(&p, caps, items, local, k, base, assign, types, cost);
     pk_free(&p);
@@ -670,7 +786,8 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
         int32_t c = o->force_crit >= 0
                         ? o->force_crit
                         : orc_criterion_digit(ck, (uint64_t)((int64_t)I * P + r), t);
-        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL);
+        place(&p, caps, n, w[items[order[t]]], c, 1, o->type_rule, 0, smin[t], st, NULL, NULL,
+              NULL);
       }
       int64_t c = packer_cost(&p, caps);
       if (best_r < 0 || c < best_cost) {
@@ -690,7 +807,8 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
                       ? o->force_crit
                       : orc_criterion_digit(ck, (uint64_t)((int64_t)I * P + best_r), t);
       placed_items[t] = items[order[t]];
-      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, 0, NULL, NULL, NULL);
+      local[t] = place(&p, caps, n, w[placed_items[t]], c, 1, o->type_rule, 0, 0, NULL, NULL, NULL,
+                       NULL);
     }
     base += emit_packer(&p, caps, placed_items, local, k, base, assign, types, cost);
     pk_free(&p);
@@ -734,7 +852,7 @@ int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
 static int32_t orc_pack_run(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                             int32_t heuristic, const orc_opts* opt, int32_t* assign,
                             int32_t* types, int64_t* cost, orc_stats* stats) {
-  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0, 0};
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0, 0, 0};
   const orc_opts* o = opt ? opt : &def;
   if (!assign || !types || !cost) return ORC_E_NULL;
   int32_t rc = validate(w, m, caps, n, heuristic, o);
@@ -769,7 +887,7 @@ int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
     for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
   for (int32_t t = 0; t < m; ++t) {
     items[t] = t;
-    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, 0, NULL, NULL, NULL);
+    local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, 0, NULL, NULL, NULL, NULL);
   }
   *cost = 0;
   int32_t nb = emit_packer(&p, caps, items, local, m, 0, assign, types, cost);

@@ -47,7 +47,9 @@ typedef struct {
  * run (chosen = type opened, plain_type = the base rule's type, feasible =
  * types holding the item), or a placement of the first heuristic where the
  * three criteria pick different bins under the learned criterion rule
- * (chosen = criterion used, plain_type = Rule 3's draw, feasible = 7) */
+ * (chosen = criterion used, plain_type = Rule 3's draw, feasible = 7), or a
+ * contested placement of a plain run under a choice rule (chosen = 1 when a
+ * new bin opened, else 0; plain_type = 0; feasible = 3) */
 typedef struct {
   int32_t position;   /* position of the item in processing order      */
   int32_t weight;
@@ -81,6 +83,14 @@ typedef struct {
   int32_t criterion_rule; /* H1 only: 0 = Rule 3's draw; 1 = the model (n_out
                              >= 3) picks FF/BF/WF where they differ (see
                              h1_learned_criterion); needs force_crit = -1  */
+  int32_t choice_rule;    /* plain FF/BF/WF with type_rule LARGEST and
+                             downsize 1 only (see plain_choice): 0 = the
+                             criterion's bin always; 1 = the same, but the
+                             run's decisions are its contested placements
+                             (forcing and the trace index those); 2 = the
+                             model (n_out >= 2) chooses at each contested
+                             placement between the criterion's bin (output
+                             0) and a new bin (output 1)                    */
 } orc_opts;
 
 typedef struct {
@@ -138,6 +148,16 @@ int32_t orc_rollout_label(const int32_t* w, int32_t m, const int32_t* caps, int3
 int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                              int32_t crit, int32_t d, int32_t type_rule, int32_t downsize,
                              int64_t* values);
+
+/* Depth-2 lookahead label of contested placement d of a plain run with
+ * criterion crit under the largest type rule with downsizing: for k1 in
+ * {0 = the criterion's bin, 1 = a new bin}, V(k1) = min over k2 of the
+ * downsized cost of the run with k1 at d and k2 at d+1 (the criterion's bin
+ * elsewhere); the label is argmin V, 0 on ties.  values[2] receives V.
+ * Returns the label, ORC_E_OPTION when the run has fewer than d+1 contested
+ * placements, or another negative code. */
+int32_t orc_choice_label(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
+                         int32_t crit, int32_t d, int64_t* values);
 
 /* lower bounds on the optimum */
 int64_t orc_lb_sum(const int32_t* w, int32_t m);
