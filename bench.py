@@ -658,7 +658,8 @@ def orderings_leg(V, torch, steps, warmup, cpu_sample):
 def learned_leg(V, torch, steps, cpu_sample):
     """The committed scorers on 4096 held-out instances (m = 2000, n = 5):
     mean cost/LB of plain and learned with a paired bootstrap interval, the
-    largest-type rule with downsizing beside them, and instances/s of each."""
+    largest-type rule with downsizing beside them, the learned bin choice
+    (on that rule) against it, and instances/s of each."""
     import numpy as np
 
     import oracle
@@ -685,9 +686,18 @@ def learned_leg(V, torch, steps, cpu_sample):
             raw = f.read()
         models[crit] = raw
         dm = torch.tensor(np.frombuffer(raw, dtype=np.uint8).copy(), device="cuda")
-        for name, kw in (("plain", {}),
-                         ("learned", dict(type_rule=V.TYPE_LEARNED, model_ptr=dm.data_ptr())),
-                         ("largest+downsize", dict(type_rule=V.TYPE_LARGEST, downsize=True))):
+        variants = [("plain", {}),
+                    ("learned", dict(type_rule=V.TYPE_LEARNED, model_ptr=dm.data_ptr())),
+                    ("largest+downsize", dict(type_rule=V.TYPE_LARGEST, downsize=True))]
+        choice_path = os.path.join(MODEL_DIR, f"choice_{crit}.bin")
+        if os.path.exists(choice_path):
+            with open(choice_path, "rb") as f:
+                craw = f.read()
+            models[crit + "+choice"] = craw
+            cm = torch.tensor(np.frombuffer(craw, dtype=np.uint8).copy(), device="cuda")
+            variants.append(("learned choice", dict(type_rule=V.TYPE_LARGEST, downsize=True,
+                                                    choice_rule=2, model_ptr=cm.data_ptr())))
+        for name, kw in variants:
             o = outputs_like(V, torch, db)
             p = V.Plan(o, crit, graph=True, autotune=True, **kw)
             ms = time_plan(torch, p, stream, steps, 2)
@@ -702,6 +712,9 @@ def learned_leg(V, torch, steps, cpu_sample):
         r["learned_minus_plain"] = {"mean": d, "ci95": ci}
         d, ci = paired(runs["learned"][0], runs["largest+downsize"][0])
         r["learned_minus_largest_downsize"] = {"mean": d, "ci95": ci}
+        if "learned choice" in runs:
+            d, ci = paired(runs["learned choice"][0], runs["largest+downsize"][0])
+            r["learned_choice_minus_largest_downsize"] = {"mean": d, "ci95": ci}
         out[crit] = r
     if cpu_sample > 0:
         oracle.build()

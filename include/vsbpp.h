@@ -133,6 +133,17 @@ typedef struct vsbpp_options {
                                take it (the other calls: VSBPP_E_MODEL);
                                with another heuristic or a forced criterion:
                                VSBPP_E_OPTION.                                */
+  int32_t choice_rule;      /* plain FF/BF/WF under VSBPP_TYPE_LARGEST with
+                               downsize 1 and no bound on the open bins (else
+                               VSBPP_E_OPTION): 0 (default) the criterion's
+                               bin always; 1 the same, but the decisions of
+                               the run (decision hooks) are its contested
+                               placements; 2 a trained network chooses at
+                               each contested placement between the
+                               criterion's bin and a new bin (see the learned
+                               bin choice below).  2 needs a model, so only
+                               vsbpp_pack_batch_ex and vsbpp_plan_create_ex
+                               take it (the other calls: VSBPP_E_MODEL).     */
 } vsbpp_options;
 
 void vsbpp_options_init(vsbpp_options* opt);
@@ -360,12 +371,16 @@ typedef struct vsbpp_model {
  * not hold the item is ignored; d = -1 forces nothing).  At decision d,
  * features[16e..16e+15] receive the decision features and info[2e] the mask
  * of types holding the item (bit k for B_k >= w), info[2e+1] the smallest
- * fitting type; entries whose run has no decision d leave them untouched. */
+ * fitting type; entries whose run has no decision d leave them untouched.
+ * count[e] receives the number of decisions of entry e's run (plain
+ * FF/BF/WF; appended last, so a caller that zero-fills the struct before
+ * setting the fields it knows keeps working). */
 typedef struct vsbpp_decisions {
   const int32_t* src;
   const int32_t* force;
   float* features;
   int32_t* info;
+  int32_t* count;
 } vsbpp_decisions;
 
 /* Learned criterion of the first heuristic (opt->criterion_rule = 1, Section
@@ -384,10 +399,31 @@ typedef struct vsbpp_decisions {
  * The network's arithmetic is that of the bin-type scorer.  A model with
  * fewer than 3 outputs gives VSBPP_E_MODEL in every instance's d_nbins. */
 
+/* Learned bin choice (opt->choice_rule = 2; plain FF/BF/WF, largest type
+ * rule, downsizing; Section 1 leaves the choice of bins and types beyond the
+ * three rules open).  After downsizing a bin of load L costs c(L), the
+ * smallest capacity >= L.  Placing item w into the criterion's bin (load L)
+ * is contested when c(L + w) > c(L).  There the network (n_out >= 2;
+ * outputs 0 = keep the criterion's bin, 1 = open a new bin of type B_1)
+ * is evaluated on these fp32 features ("a / b" is a times the fp32
+ * reciprocal of b): 0..10 as features 0..10 of a bin-type decision (the
+ * histogram over all bins, every bin with capacity B_1), then
+ *   11 (B_1 - L - w) / B_1     12 (c(L + w) - c(L)) / B_1
+ *   13 c(w) / B_1              14 (c(L + w) - L - w) / B_1
+ *   15 (c(L) - L) / B_1
+ * A new bin opens only when output 1 is strictly larger and both are
+ * finite.  Bins opened because nothing fits are not decisions.  The
+ * decision hooks then index contested placements: force t1/t2 are 0 (keep)
+ * or 1 (open), info[2e] = 3 (both allowed) and info[2e+1] = 0 (the plain
+ * choice).  A model with fewer than 2 outputs gives VSBPP_E_MODEL in every
+ * instance's d_nbins.  The network's arithmetic is that of the bin-type
+ * scorer. */
+
 /* vsbpp_pack_batch with a scorer (d_model: device pointer to a vsbpp_model,
  * e.g. from vsbpp_model_load, required when opt->type_rule is
- * VSBPP_TYPE_LEARNED or opt->criterion_rule is 1 -- VSBPP_E_MODEL when it is
- * NULL -- else ignored) and decision hooks (dec may be NULL).  The bin-type
+ * VSBPP_TYPE_LEARNED, opt->criterion_rule is 1 or opt->choice_rule is 2 --
+ * VSBPP_E_MODEL when it is NULL -- else ignored) and decision hooks (dec may
+ * be NULL).  The bin-type
  * scorer and the hooks above are for plain FF/BF/WF.  With H1, dec may carry
  * features and info only (src and force: VSBPP_E_OPTION), in another
  * layout: for the item at position q of instance i (offset off_i of its

@@ -61,6 +61,7 @@ class Options(ctypes.Structure):
         ("active_limit", ctypes.c_int32),
         ("downsize", ctypes.c_int32),
         ("criterion_rule", ctypes.c_int32),
+        ("choice_rule", ctypes.c_int32),
     ]
 
 
@@ -109,7 +110,7 @@ def lib():
 
 def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT,
             force_crit: int = -1, active_limit: int = 0, downsize: bool = False,
-            criterion_rule: int = 0) -> Options:
+            criterion_rule: int = 0, choice_rule: int = 0) -> Options:
     o = Options()
     lib().vsbpp_options_init(ctypes.byref(o))
     o.seed = seed & (2**64 - 1)
@@ -120,6 +121,7 @@ def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMAL
     o.active_limit = active_limit
     o.downsize = int(downsize)
     o.criterion_rule = int(criterion_rule)
+    o.choice_rule = int(choice_rule)
     return o
 
 
@@ -256,13 +258,14 @@ class DeviceBatch:
 def pack_batch(db: DeviceBatch, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
                type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, stream=None,
                use_order: bool = True, use_seeds: bool = True, active_limit: int = 0,
-               downsize: bool = False) -> None:
+               downsize: bool = False, choice_rule: int = 0) -> None:
     """Launches vsbpp_pack_batch on the given torch stream (default: current).
     Results land in db.assignment / db.bin_types / db.nbins / db.cost."""
     import torch
 
     s = stream if stream is not None else torch.cuda.current_stream()
-    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize)
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize,
+                choice_rule=choice_rule)
     ptr = lambda x: None if x is None else x.data_ptr()
     rc = lib().vsbpp_pack_batch(
         db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
@@ -334,7 +337,8 @@ class Plan:
                  graph: bool = False, autotune: bool = False, seed: int = 0, s1: int = 10,
                  s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
                  use_order: bool = True, use_seeds: bool = True, model_ptr=None,
-                 active_limit: int = 0, downsize: bool = False, criterion_rule: int = 0):
+                 active_limit: int = 0, downsize: bool = False, criterion_rule: int = 0,
+                 choice_rule: int = 0):
         L = _plan_lib()
         ptr = lambda x: None if x is None else x.data_ptr()
         self.db = db
@@ -343,7 +347,8 @@ class Plan:
             ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
             db.max_items, db.max_types, db.max_cap,
             ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
-        o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize, criterion_rule)
+        o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize, criterion_rule,
+                    choice_rule)
         lp = None
         if launch is not None:
             lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
@@ -424,7 +429,8 @@ class Model(ctypes.Structure):
 
 class _Decisions(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("force", ctypes.c_void_p),
-                ("features", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+                ("features", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("count", ctypes.c_void_p)]
 
 
 def _learn_lib():
@@ -475,7 +481,7 @@ def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force
                   features=None, info=None, nbins=None, cost=None, seed: int = 0,
                   type_rule: int = TYPE_SMALLEST_FIT, stream=None,
                   active_limit: int = 0, downsize: bool = False, criterion_rule: int = 0,
-                  force_crit: int = -1) -> None:
+                  force_crit: int = -1, choice_rule: int = 0, count=None) -> None:
     """vsbpp_pack_batch_ex.  With `src` (int32 tensor [E]) the batch has E
     entries reading instance src[e]; nbins/cost then receive E results (pass
     tensors of size E)."""
@@ -489,9 +495,9 @@ def pack_batch_ex(db: DeviceBatch, heuristic, *, model_ptr=None, src=None, force
         d.nbins = nbins.data_ptr()
     if cost is not None:
         d.cost = cost.data_ptr()
-    dec = _Decisions(ptr(src), ptr(force), ptr(features), ptr(info))
+    dec = _Decisions(ptr(src), ptr(force), ptr(features), ptr(info), ptr(count))
     o = options(seed, type_rule=type_rule, active_limit=active_limit, downsize=downsize,
-                criterion_rule=criterion_rule, force_crit=force_crit)
+                criterion_rule=criterion_rule, force_crit=force_crit, choice_rule=choice_rule)
     rc = L.vsbpp_pack_batch_ex(ctypes.byref(d), _heur(heuristic), ctypes.byref(o), model_ptr,
                                ctypes.byref(dec), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:

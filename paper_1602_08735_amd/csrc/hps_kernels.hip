@@ -537,8 +537,11 @@ __device__ __forceinline__ uint32_t nth_perm(int r, int k) {
 
 constexpr int kMaxSubset = 6;
 
+// H2 over LanePacker bins for wide batches (B_1 > 32767 or more than 65535
+// items: 64-bit keys); narrower batches take k_h2s below.
 template <typename K>
 __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group) {
+  static_assert(sizeof(K) == 8, "k_h2 runs wide batches only");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_caps[kMaxTypes];
   using GK = typename std::conditional<sizeof(K) == 4, uint32_t, uint64_t>::type;
@@ -1079,10 +1082,6 @@ hipError_t launch_h2_grid(const BatchArgs& a, H2Kernel k, int nbslots, int block
     { static bool done3 = false; e = raise_lds(k_h2s, lds, done3); }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_h2s, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
-  } else if (k == H2Kernel::kPacked) {
-    { static bool done4 = false; e = raise_lds(k_h2<uint32_t>, lds, done4); }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_h2<uint32_t>, dim3(blocks), dim3(block), lds, s, a, nbslots, group);
   } else {
     { static bool done5 = false; e = raise_lds(k_h2<uint64_t>, lds, done5); }
     if (e != hipSuccess) return e;
@@ -1107,9 +1106,7 @@ int h1_blocks_per_cu(bool wide, int block, size_t lds, bool learned) {
 }
 
 int h2_blocks_per_cu(H2Kernel k, int block, size_t lds) {
-  return k == H2Kernel::kSlim     ? occ(k_h2s, block, lds)
-         : k == H2Kernel::kPacked ? occ(k_h2<uint32_t>, block, lds)
-                                  : occ(k_h2<uint64_t>, block, lds);
+  return k == H2Kernel::kSlim ? occ(k_h2s, block, lds) : occ(k_h2<uint64_t>, block, lds);
 }
 
 namespace {

@@ -35,6 +35,8 @@ struct BatchArgs {
   int32_t active_limit;     // plain FF/BF/WF: bins open at once (0: no limit)
   int32_t downsize;         // 1: a pass after packing gives every bin its smallest type
   int32_t criterion_rule;   // H1: 0 Rule 3's draw, 1 the model picks FF/BF/WF
+  int32_t choice_rule;      // plain FF/BF/WF (largest type, downsizing): 0 off, 1 contested
+                            // placements are the decisions, 2 the model keeps or opens
   int32_t s1;               // H1 items per sublist
   int32_t s2;               // H2 subset size
   int32_t slots;            // plain kernel: LDS key slots per wavefront
@@ -45,6 +47,7 @@ struct BatchArgs {
   const int32_t* force;     // [3*num] (d, t1, t2), or null
   float* feat_out;          // [16*num], or null
   int32_t* info_out;        // [2*num], or null
+  int32_t* count_out;       // [num] decisions of each run, or null
   const vsbpp_model* model; // type_rule 2
   // plain kernel: a device region of per-wave bytes per instance that holds
   // the wavefront's arrays when they do not fit LDS, or null
@@ -86,7 +89,12 @@ __host__ __device__ inline bool plain_ds_loads(const BatchArgs& a) {
 }
 size_t plain_lds_block_extra(bool learned);
 inline bool plain_ext(const BatchArgs& a) {
-  return a.src || a.force || a.feat_out || a.info_out || a.type_rule == 2;
+  return a.src || a.force || a.feat_out || a.info_out || a.count_out || a.type_rule == 2 ||
+         a.choice_rule == 2;
+}
+// plain runs that evaluate the network (bin-type scorer or bin choice)
+__host__ __device__ inline bool plain_scored(const BatchArgs& a) {
+  return a.type_rule == 2 || a.choice_rule == 2;
 }
 // learned: the variant that scores the criterion (or dumps its features)
 size_t h1_lds_bytes(int nbslots, int s1, int block, bool wide, bool learned = false);
@@ -99,9 +107,8 @@ constexpr int32_t kErrModel = -9;
 // more than 128 registers per lane)
 constexpr int kH1LearnedMaxBlock = 512;
 // H2 kernels: one 32-bit key word per bin with a chunk of resolved positions
-// (the fast form), one packed 32-bit word per bin (when the fast form's LDS
-// does not fit), 64-bit bins (wide)
-enum class H2Kernel { kSlim, kPacked, kWide };
+// (the fast form), 64-bit bins (wide batches)
+enum class H2Kernel { kSlim, kWide };
 size_t h2_lds_bytes(int nbslots, int block, int group, H2Kernel k);
 int h2_group(int s2);
 hipError_t launch_best_of(const int64_t* cost, int32_t num, int64_t* out, hipStream_t s);

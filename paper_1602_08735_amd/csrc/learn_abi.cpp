@@ -81,15 +81,16 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     if (rc != VSBPP_OK) return rc;
   }
   if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
-  const bool hooks = dec && (dec->src || dec->force || dec->features || dec->info);
+  const bool hooks = dec && (dec->src || dec->force || dec->features || dec->info || dec->count);
   if (heuristic == VSBPP_H1) {
     // the first heuristic takes the learned criterion and the feature dump
     // of its contested placements; nothing else here
-    if (learned || (dec && (dec->src || dec->force))) return VSBPP_E_OPTION;
+    if (learned || (dec && (dec->src || dec->force || dec->count))) return VSBPP_E_OPTION;
   } else if ((learned || hooks) && heuristic > VSBPP_WF) {
     return VSBPP_E_OPTION;
   }
-  if ((learned || o.criterion_rule == 1) && !d_model) return VSBPP_E_MODEL;
+  if ((learned || o.criterion_rule == 1 || o.choice_rule == 2) && !d_model)
+    return VSBPP_E_MODEL;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
   vsbpp::BatchArgs a{};
   a.w = b->weights;
@@ -112,6 +113,7 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
   a.criterion_rule = o.criterion_rule;
+  a.choice_rule = o.choice_rule;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   if (dec) {
@@ -119,8 +121,11 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
     a.force = dec->force;
     a.feat_out = dec->features;
     a.info_out = dec->info;
+    a.count_out = dec->count;
   }
-  a.model = (o.type_rule == VSBPP_TYPE_LEARNED || o.criterion_rule == 1) ? d_model : nullptr;
+  a.model = (o.type_rule == VSBPP_TYPE_LEARNED || o.criterion_rule == 1 || o.choice_rule == 2)
+                ? d_model
+                : nullptr;
   return vsbpp::enqueue_batch(a, heuristic, vsbpp::default_cfg(heuristic, a), nullptr, nullptr,
                               (hipStream_t)hip_stream);
 }

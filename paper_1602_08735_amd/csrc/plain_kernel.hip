@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
   // the scorer's weights sit at the start of LDS: every weight read is then
   // one aligned 16-byte word at an immediate offset from the lane's base
   ModelLds* md = reinterpret_cast<ModelLds*>(smem);
-  const size_t model_bytes = (EXT && a.type_rule == 2) ? kModelLdsBytes : 0;
+  const size_t model_bytes = (EXT && plain_scored(a)) ? kModelLdsBytes : 0;
   const size_t pid_bytes = ((size_t)a.slots * sizeof(Pid) + 15) & ~(size_t)15;
   const size_t smin_bytes = (((size_t)a.max_items + 63) / 64 * 4 + 15) & ~(size_t)15;
   K* keys;
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
   const bool dsl = DSL && plain_ds_loads(a);
   if constexpr (!SPILL) carve(smem + model_bytes + (size_t)wave * (size_t)per_wave);
   if constexpr (EXT) {
-    if (a.type_rule == 2) {
+    if (plain_scored(a)) {
       stage_model(a.model, md);
       __syncthreads();
     }
@@ -352,6 +352,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       if (ballot(lane < n && (cap_lane <= 0 || cap_lane >= prev))) err = kErrCaps;
       B1 = readlane(cap_lane, 0);
       if (!err && B1 > a.max_cap) err = kErrSize;
+    }
+    // the bin choice scores two outputs (keep, open)
+    if constexpr (EXT) {
+      if (!err && a.choice_rule == 2 && md->n_out < 2) err = kErrModel;
     }
     const int m = (int)m64;
     const int nch = (m + 63) >> 6;
@@ -533,6 +537,91 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             nk = best;
           }
         }
+        // decision features 0..10 (wave-uniform values): the item, the items
+        // after it, the bins so far and their room histogram
+        auto state_features = [&](float (&x)[16]) {
+          const int qq = (c << 6) + jj;
+          const int rem = m - qq - 1;
+          const int64_t rsum = total - (int64_t)placed - w;
+          int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
+          after = min(after, next_min);
+          const float inv_b1 = 1.0f / (float)B1;
+          const float inv_m = 1.0f / (float)m;
+          x[0] = (float)w * inv_b1;
+          x[1] = (float)rem * inv_m;
+          // with 32-bit keys m <= 65535 and B_1 <= 32767, so the remaining
+          // weight fits int32 (whose conversion rounds as int64's does)
+          const float frs = sizeof(K) == 4 ? (float)(int32_t)rsum : (float)rsum;
+          x[2] = rem > 0 ? (frs / (float)rem) * inv_b1 : 0.0f;
+          x[3] = rem > 0 ? (float)after * inv_b1 : 1.0f;
+          x[4] = (float)nb * inv_m;
+          const float inv_den = 1.0f / (float)(nb > 0 ? nb : 1);
+          const int4 h03 = *reinterpret_cast<const int4*>(hist);
+          const int4 h47 = *reinterpret_cast<const int4*>(hist + 4);
+          x[5] = (float)h03.x * inv_den;
+          x[6] = (float)h03.y * inv_den;
+          x[7] = (float)h03.z * inv_den;
+          x[8] = (float)h03.w * inv_den;
+          x[9] = (float)h47.x * inv_den;
+          x[10] = (float)h47.y * inv_den;
+        };
+        if constexpr (EXT) {
+          // Bin choice (largest type rule, downsizing): every bin has capacity
+          // B_1 and costs c(L), the smallest capacity >= its load L.  The
+          // placement into the criterion's bin is contested when c(L + w) >
+          // c(L); the capacities are distinct and decreasing, so that is when
+          // fewer types hold L + w than hold L.
+          if (a.choice_rule != 0 && p >= 0) {
+            const int32_t ra = (int32_t)room_of<CRIT>(nk);  // room after the item
+            const int32_t L = B1 - ra - w;
+            const uint64_t hb = ballot(cap_lane >= L);
+            const uint64_t ha = ballot(cap_lane >= L + w);
+            if (hb != ha) {
+              const int d = nev;
+              nev = uniform(nev + 1);
+              const bool dump = d == fd && (a.feat_out || a.info_out);
+              bool open = false;
+              if (a.choice_rule == 2 || dump) {
+                const float inv_b1 = 1.0f / (float)B1;
+                const int32_t cb = readlane(cap_lane, (int)__popcll(hb) - 1);
+                const int32_t ca = readlane(cap_lane, (int)__popcll(ha) - 1);
+                const int32_t cw = readlane(cap_lane, (int)__popcll(ballot(cap_lane >= w)) - 1);
+                float x[16];
+                state_features(x);
+                x[11] = (float)ra * inv_b1;
+                x[12] = (float)(ca - cb) * inv_b1;
+                x[13] = (float)cw * inv_b1;
+                x[14] = (float)(ca - L - w) * inv_b1;
+                x[15] = (float)(cb - L) * inv_b1;
+                if (a.choice_rule == 2) {
+                  const float z = mlp_forward_wave(md, x, hbuf, lane);
+                  const float z0 = __uint_as_float(readlane(__float_as_uint(z), 0));
+                  const float z1 = __uint_as_float(readlane(__float_as_uint(z), 1));
+                  // a new bin only on a strictly larger score; non-finite
+                  // scores keep the criterion's bin
+                  open = __builtin_isfinite(z0) && __builtin_isfinite(z1) && z1 > z0;
+                }
+                if (dump) {
+                  if (a.feat_out && lane < 16) {
+                    float xv = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) xv = lane == k ? x[k] : xv;
+                    a.feat_out[16 * (int64_t)inst + lane] = xv;
+                  }
+                  if (a.info_out && lane == 0) {
+                    a.info_out[2 * (int64_t)inst] = 3;      // keep and open both allowed
+                    a.info_out[2 * (int64_t)inst + 1] = 0;  // the plain choice keeps
+                  }
+                }
+              }
+              if (fd >= 0) {  // forced decisions (rollouts) only
+                const int ft = d == fd ? ft1 : (d == fd + 1 ? ft2 : -1);
+                if (ft == 0 || ft == 1) open = ft == 1;
+              }
+              if (open) p = -1;
+            }
+          }
+        }
         if (p >= 0) {
           // Rule 4: place into the chosen open bin
           put_key(mine, lane, p, nk);
@@ -583,38 +672,16 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           const uint64_t fm = ballot(cap_lane >= w);
           const int smallest = (int)__popcll(fm) - 1;
           int t = a.type_rule == 1 ? 0 : smallest;
-          if constexpr (EXT) {
+          // under the bin choice the decisions are contested placements, and
+          // a bin opened because nothing fits has type 0 (largest type rule)
+          if (EXT && a.choice_rule == 0) {
             const int d = nev;
             nev = uniform(nev + 1);
             const bool dump = d == fd && (a.feat_out || a.info_out);
             // features only where the scorer has a choice (or a dump asks)
             if ((a.type_rule == 2 && smallest > 0) || dump) {
-              // decision features (wave-uniform values)
-              const int qq = (c << 6) + jj;
-              const int rem = m - qq - 1;
-              const int64_t rsum = total - (int64_t)placed - w;
-              int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
-              after = min(after, next_min);
-              const float inv_b1 = 1.0f / (float)B1;
-              const float inv_m = 1.0f / (float)m;
               float x[16];
-              x[0] = (float)w * inv_b1;
-              x[1] = (float)rem * inv_m;
-              // with 32-bit keys m <= 65535 and B_1 <= 32767, so the remaining
-              // weight fits int32 (whose conversion rounds as int64's does)
-              const float frs = sizeof(K) == 4 ? (float)(int32_t)rsum : (float)rsum;
-              x[2] = rem > 0 ? (frs / (float)rem) * inv_b1 : 0.0f;
-              x[3] = rem > 0 ? (float)after * inv_b1 : 1.0f;
-              x[4] = (float)nb * inv_m;
-              const float inv_den = 1.0f / (float)(nb > 0 ? nb : 1);
-              const int4 h03 = *reinterpret_cast<const int4*>(hist);
-              const int4 h47 = *reinterpret_cast<const int4*>(hist + 4);
-              x[5] = (float)h03.x * inv_den;
-              x[6] = (float)h03.y * inv_den;
-              x[7] = (float)h03.z * inv_den;
-              x[8] = (float)h03.w * inv_den;
-              x[9] = (float)h47.x * inv_den;
-              x[10] = (float)h47.y * inv_den;
+              state_features(x);
 #pragma unroll
               for (int k = 0; k < 4; ++k) x[11 + k] = xcap[k];
               x[15] = (float)w * __uint_as_float(readlane(__float_as_uint(inv_cap_lane), smallest));
@@ -701,6 +768,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     if (lane == 0) {
       a.nbins[inst] = nb;
       a.cost[inst] = out_cost;
+      if (EXT && a.count_out) a.count_out[inst] = nev;
     }
   }
 }
@@ -709,7 +777,7 @@ template <int CRIT, typename K, bool EXT, bool SPILL, int OPT>
 hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
   const size_t lds = SPILL ? 0
                            : per_wave * (size_t)wpb +
-                                 (EXT ? plain_lds_block_extra(a.type_rule == 2) : 0);
+                                 (EXT ? plain_lds_block_extra(plain_scored(a)) : 0);
   auto kern = k_plain<CRIT, K, EXT, SPILL, OPT>;
   static bool raised = false;
   if (lds > 65536 && !raised) {
@@ -789,7 +857,7 @@ hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
 
 
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave) {
-  const bool ext = plain_ext(a), learned = a.type_rule == 2, spill = a.spill != nullptr;
+  const bool ext = plain_ext(a), learned = plain_scored(a), spill = a.spill != nullptr;
   const bool bnd = a.active_limit > 0, dsl = plain_ds_loads(a);
   const size_t lw = lds_per_wave;
   if (!wide) {

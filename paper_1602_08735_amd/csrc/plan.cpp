@@ -48,7 +48,8 @@ int bucket(long long x) {
 
 std::string tune_key(int heuristic, const vsbpp::BatchArgs& a) {
   std::ostringstream k;
-  k << "v2-h" << heuristic << (a.type_rule == 2 ? "L" : "") << (a.criterion_rule == 1 ? "C" : "") << "-m" << bucket(a.max_items)
+  k << "v2-h" << heuristic << (a.type_rule == 2 ? "L" : "") << (a.criterion_rule == 1 ? "C" : "")
+    << (a.choice_rule == 2 ? "B" : "") << "-m" << bucket(a.max_items)
     << "-t" << a.max_types << "-c"
     << (a.max_cap > 0x7FFF ? 1 : 0) << "-n" << bucket(a.num) << "-s"
     << (heuristic == VSBPP_H1 ? a.s1 : heuristic == VSBPP_H2 ? a.s2 : 0);
@@ -105,6 +106,10 @@ int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
   // mean time of a burst of shape c, or a negative value when c does not
   // apply to the batch
   auto time_cfg = [&](const vsbpp::LaunchCfg& c, float* out) -> int32_t {
+    if (vsbpp::check_cfg(c, p->heuristic, p->args) != VSBPP_OK) {
+      *out = -1.0f;
+      return VSBPP_OK;
+    }
     p->cfg = c;
     for (int i = 0; i < 2; ++i) {  // warm-up
       const int32_t r = run_eager(p, s);
@@ -227,7 +232,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   int32_t rc = vsbpp::check_options_public(o);
   if (rc == VSBPP_OK) rc = vsbpp::check_heuristic_options_public(o, heuristic);
   if (rc != VSBPP_OK) return rc;
-  if ((learned || o.criterion_rule == 1) && !d_model) return VSBPP_E_MODEL;
+  if ((learned || o.criterion_rule == 1 || o.choice_rule == 2) && !d_model) return VSBPP_E_MODEL;
   if (learned) o.type_rule = VSBPP_TYPE_LEARNED;
   if (!vsbpp::device_info().ok) return VSBPP_E_DEVICE;
 
@@ -253,9 +258,10 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
   a.criterion_rule = o.criterion_rule;
+  a.choice_rule = o.choice_rule;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
-  a.model = (learned || o.criterion_rule == 1) ? d_model : nullptr;
+  a.model = (learned || o.criterion_rule == 1 || o.choice_rule == 2) ? d_model : nullptr;
   p->heuristic = heuristic;
 
   if (hipMalloc(&p->workspace, sizeof(int32_t) * ((size_t)a.num + 1)) != hipSuccess) {

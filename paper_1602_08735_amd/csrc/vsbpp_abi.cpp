@@ -57,6 +57,7 @@ int32_t check_options(const vsbpp_options& o) {
   if (o.active_limit < 0) return VSBPP_E_OPTION;
   if (o.downsize != 0 && o.downsize != 1) return VSBPP_E_OPTION;
   if (o.criterion_rule != 0 && o.criterion_rule != 1) return VSBPP_E_OPTION;
+  if (o.choice_rule < 0 || o.choice_rule > 2) return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
 
@@ -64,6 +65,12 @@ int32_t check_options(const vsbpp_options& o) {
 int32_t check_heuristic_options(const vsbpp_options& o, int32_t heuristic) {
   if (o.active_limit > 0 && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
   if (o.criterion_rule == 1 && (heuristic != VSBPP_H1 || o.force_criterion != -1))
+    return VSBPP_E_OPTION;
+  // the bin choice compares bins by their downsized capacity: plain rules,
+  // bins opened at B_1, every bin downsized, no bound on the open bins
+  if (o.choice_rule != 0 &&
+      (heuristic > VSBPP_WF || o.type_rule != VSBPP_TYPE_LARGEST || o.downsize != 1 ||
+       o.active_limit != 0))
     return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
@@ -135,7 +142,7 @@ int32_t plain_shape(const BatchArgs& a, PlainShape* sh) {
   if (!wide && sh->slots > 65536) return VSBPP_E_SIZE;
   const bool ext = plain_ext(a);
   sh->per_wave = plain_lds_per_wave(sh->slots, a.max_items, wide, ext, plain_ds_loads(a));
-  const size_t extra = ext ? plain_lds_block_extra(a.type_rule == 2) : 0;
+  const size_t extra = ext ? plain_lds_block_extra(plain_scored(a)) : 0;
   sh->spill = (size_t)device_info().max_lds_block < extra + sh->per_wave;
   if (sh->spill) {
     if (ext) return VSBPP_E_SIZE;
@@ -152,16 +159,13 @@ int h_nbslots(int heuristic, const BatchArgs& a) {
   return round_up(a.max_types + 2 * (heuristic == VSBPP_H1 ? a.s1 : a.s2), 4);
 }
 
-// the H2 kernel for a workgroup size: the slim kernel (32-bit bin words plus
-// a chunk of resolved positions) when it fits the workgroup's LDS, else the
-// packed one (64-bit bins for wide batches)
-H2Kernel h2_kernel(const BatchArgs& a, int block) {
-  if (is_wide(a)) return H2Kernel::kWide;
-  const size_t budget = (size_t)(device_info().max_lds_block - kStaticLdsReserve);
-  const int g = h2_group(a.s2);
-  const int b = block < g ? g : (block / g) * g;
-  return h2_lds_bytes(h_nbslots(VSBPP_H2, a), b, g, H2Kernel::kSlim) <= budget ? H2Kernel::kSlim
-                                                                                : H2Kernel::kPacked;
+// the H2 kernel: the slim kernel (32-bit bin words plus a chunk of resolved
+// positions), or 64-bit bins for wide batches.  At the largest subset (s2 =
+// 6, 16 types: 28 slots) the slim kernel needs 95 KB of LDS per 768-thread
+// workgroup, well inside gfx950's 160 KB; h_fit_block shrinks larger
+// workgroups to fit.
+H2Kernel h2_kernel(const BatchArgs& a, int /*block*/) {
+  return is_wide(a) ? H2Kernel::kWide : H2Kernel::kSlim;
 }
 
 size_t h_lds(int heuristic, const BatchArgs& a, int block) {
@@ -271,7 +275,8 @@ std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a) {
         }
       } else {
         const int gran = heuristic == VSBPP_H2 ? h2_group(a.s2) : 64;
-        for (int b = gran; b <= 1024; b *= 2) {
+        const int bmax = (heuristic == VSBPP_H1 && h1_learned(a)) ? kH1LearnedMaxBlock : 1024;
+        for (int b = gran; b <= bmax; b *= 2) {
           if (b % gran) continue;
           LaunchCfg c;
           c.mode = mode;
@@ -321,6 +326,7 @@ BatchArgs batch_args(const vsbpp_batch& b, const vsbpp_options& o) {
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
   a.criterion_rule = o.criterion_rule;
+  a.choice_rule = o.choice_rule;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   return a;
@@ -452,6 +458,7 @@ void vsbpp_options_init(vsbpp_options* opt) {
   opt->active_limit = 0;
   opt->downsize = 0;
   opt->criterion_rule = 0;
+  opt->choice_rule = 0;
 }
 
 const char* vsbpp_strerror(int32_t code) {
@@ -487,7 +494,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   rc = check_options(o);
   if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
   if (rc != VSBPP_OK) return rc;
-  if (o.criterion_rule == 1) return VSBPP_E_MODEL;  // this call takes no model
+  if (o.criterion_rule == 1 || o.choice_rule == 2) return VSBPP_E_MODEL;  // this call takes no model
 
   std::lock_guard<std::mutex> lk(g_mu);
   if (!device_ok_locked()) return VSBPP_E_DEVICE;
@@ -587,7 +594,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
   int32_t rc = check_options(o);
   if (rc == VSBPP_OK) rc = check_heuristic_options(o, heuristic);
   if (rc != VSBPP_OK) return rc;
-  if (o.criterion_rule == 1) return VSBPP_E_MODEL;  // this call takes no model
+  if (o.criterion_rule == 1 || o.choice_rule == 2) return VSBPP_E_MODEL;  // this call takes no model
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!device_ok_locked()) return VSBPP_E_DEVICE;

@@ -1,5 +1,12 @@
-"""Learned bin-type scorer pipeline on the GPU: decision sampling, decision
-features, depth-2 lookahead rollout labels, training and evaluation.
+"""Learned bin-type scorer and learned bin choice on the GPU: decision
+sampling, decision features, depth-2 lookahead rollout labels, training and
+evaluation.
+
+Bin-type decisions are the items that fit no open bin (the base rule opens
+the smallest fitting type, or B_1 under the largest-type rule).  Bin-choice
+decisions (``choice=True``) are the contested placements of a plain run
+under the largest type rule with downsizing: the network keeps the
+criterion's bin (output 0) or opens a new bin (output 1).
 
 Orchestration only: every packing run, label reduction, training step and
 bound runs in the library's HIP kernels through the C ABI.  Random choices
@@ -71,6 +78,21 @@ def sample_decisions(ndec: np.ndarray, per_instance: int, rng: np.random.Generat
     return np.concatenate(src), np.concatenate(dd)
 
 
+# options of the plain run whose decisions are contested placements
+CHOICE_BASE = dict(type_rule=1, downsize=True, choice_rule=1)
+
+
+def choice_decisions(db: DeviceBatch, crit) -> np.ndarray:
+    """Number of contested placements of every instance's plain run under
+    the largest type rule with downsizing."""
+    import torch
+
+    cnt = torch.zeros(db.n, dtype=torch.int32, device="cuda")
+    pack_batch_ex(db, crit, count=cnt, **CHOICE_BASE)
+    torch.cuda.synchronize()
+    return cnt.cpu().numpy().copy()
+
+
 def plain_decisions(db: DeviceBatch, crit, type_rule: int = 0) -> np.ndarray:
     """Number of decisions of every instance's plain run under the base type
     rule (= its bins: every bin of a plain run is opened at a decision)."""
@@ -81,10 +103,10 @@ def plain_decisions(db: DeviceBatch, crit, type_rule: int = 0) -> np.ndarray:
     return db.nbins.cpu().numpy().copy()
 
 
-def decision_features(db: DeviceBatch, crit, src, d, type_rule: int = 0):
-    """Features [E,16] and (feasible mask, smallest fitting type) [E,2] of
-    decision d[e] of instance src[e]'s plain run under the base type rule
-    (device tensors)."""
+def decision_features(db: DeviceBatch, crit, src, d, type_rule: int = 0, choice: bool = False):
+    """Features [E,16] and (feasible mask, base choice) [E,2] of decision d[e]
+    of instance src[e]'s plain run under the base type rule, or of its
+    contested placement d[e] with `choice` (device tensors)."""
     import torch
 
     e = len(src)
@@ -95,22 +117,26 @@ def decision_features(db: DeviceBatch, crit, src, d, type_rule: int = 0):
     info = torch.full((e, 2), -1, dtype=torch.int32, device="cuda")
     nb = torch.empty(e, dtype=torch.int32, device="cuda")
     cost = torch.empty(e, dtype=torch.int64, device="cuda")
+    kw = CHOICE_BASE if choice else dict(type_rule=type_rule)
     pack_batch_ex(db, crit, src=t_src, force=t_force, features=feats, info=info, nbins=nb,
-                  cost=cost, type_rule=type_rule)
+                  cost=cost, **kw)
     return feats, info
 
 
 def lookahead_labels(db: DeviceBatch, crit, src, d, info, n_types: int,
                      chunk: int = 1 << 21, values: bool = False, type_rule: int = 0,
-                     downsize: bool = False):
+                     downsize: bool = False, choice: bool = False):
     """Depth-2 lookahead labels of the given decisions: one rollout entry per
     (decision, k1, k2), costs from the plain kernel with forced types (the
     base type rule elsewhere, costs after downsizing when `downsize`), labels
     from the reduction kernel (ties to the base rule's own choice: the
-    smallest fitting type, or type 0 under the largest-type rule)."""
+    smallest fitting type, or type 0 under the largest-type rule).  With
+    `choice` the decisions are contested placements, k in {0 keep, 1 open},
+    n_types is 2 and every cost is taken after downsizing; ties keep."""
     import torch
 
-    if type_rule == 1:
+    kw = CHOICE_BASE if choice else dict(type_rule=type_rule, downsize=downsize)
+    if choice or type_rule == 1:
         info = info.clone()
         info[:, 1] = 0
     src = np.asarray(src, np.int32)
@@ -131,8 +157,7 @@ def lookahead_labels(db: DeviceBatch, crit, src, d, info, n_types: int,
         t_force = torch.as_tensor(np.ascontiguousarray(force.astype(np.int32)), device="cuda")
         nb = torch.empty(m * nn, dtype=torch.int32, device="cuda")
         cost = torch.empty(m * nn, dtype=torch.int64, device="cuda")
-        pack_batch_ex(db, crit, src=t_src, force=t_force, nbins=nb, cost=cost,
-                      type_rule=type_rule, downsize=downsize)
+        pack_batch_ex(db, crit, src=t_src, force=t_force, nbins=nb, cost=cost, **kw)
         rollout_labels(cost, info[a:b].contiguous(), m, n_types, labels[a:b],
                        None if vals is None else vals[a * n_types:b * n_types])
     return (labels, vals) if values else labels
@@ -162,9 +187,11 @@ def train(x, mask, label, n_out: int, *, epochs: int = 4, batch: int = 4096,
 
 
 def evaluate(db: DeviceBatch, crit, model_ptr, repeats: int = 3, type_rule: int = 0,
-             downsize: bool = False) -> dict:
+             downsize: bool = False, choice: bool = False) -> dict:
     """Plain (the base type rule) vs learned costs on a batch, both with the
-    downsizing pass when `downsize`, their cost/LB, and instances/s of both."""
+    downsizing pass when `downsize`, their cost/LB, and instances/s of both.
+    With `choice` the learned run is the bin choice and the plain one the
+    largest type rule with downsizing."""
     import torch
 
     lb = torch.empty(3 * db.n, dtype=torch.int64, device="cuda")
@@ -172,10 +199,16 @@ def evaluate(db: DeviceBatch, crit, model_ptr, repeats: int = 3, type_rule: int 
     res = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for name in ("plain", "learned"):
-        run = (lambda: pack_batch(db, crit, type_rule=type_rule, downsize=downsize)) \
-            if name == "plain" else (
-            lambda: pack_batch_ex(db, crit, model_ptr=model_ptr, type_rule=TYPE_LEARNED,
-                                  downsize=downsize))
+        if choice:
+            run = (lambda: pack_batch(db, crit, type_rule=1, downsize=True)) \
+                if name == "plain" else (
+                lambda: pack_batch_ex(db, crit, model_ptr=model_ptr, type_rule=1,
+                                      downsize=True, choice_rule=2))
+        else:
+            run = (lambda: pack_batch(db, crit, type_rule=type_rule, downsize=downsize)) \
+                if name == "plain" else (
+                lambda: pack_batch_ex(db, crit, model_ptr=model_ptr, type_rule=TYPE_LEARNED,
+                                      downsize=downsize))
         run()
         torch.cuda.synchronize()
         ev[0].record()

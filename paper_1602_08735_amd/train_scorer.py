@@ -6,9 +6,15 @@ evaluates it against the plain rule it improves on.
     python -m paper_1602_08735_amd.train_scorer --criterion BF --base largest-ds \
         --out paper_1602_08735_amd/models/scorer_BF_ds.bin
 
+    python -m paper_1602_08735_amd.train_scorer --criterion BF --base choice \
+        --out paper_1602_08735_amd/models/choice_BF.bin
+
 Base rules: `smallest` (the smallest fitting type; costs as packed) or
 `largest-ds` (the largest type, every cost taken after the downsizing pass;
-the scorer is then evaluated with the pass as well).
+the scorer is then evaluated with the pass as well).  `choice` trains the
+learned bin choice instead: two outputs (keep the criterion's bin, open a
+new bin) at the contested placements of the largest-type run with
+downsizing, labelled by the same depth-2 lookahead over {keep, open}.
 
 Training data: decisions sampled from the plain runs of training instances of
 the uniform-batch distribution (B_1 = 200 plus 4 distinct capacities in
@@ -39,7 +45,7 @@ def main(argv=None):
     ap.add_argument("--eval-instances", type=int, default=4096)
     ap.add_argument("--eval-m", type=int, default=2000)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--base", default="smallest", choices=["smallest", "largest-ds"])
+    ap.add_argument("--base", default="smallest", choices=["smallest", "largest-ds", "choice"])
     ap.add_argument("--min-gain", type=int, default=0,
                     help="keep a label other than the base rule's choice only when its "
                          "lookahead value beats the base choice's by at least this much")
@@ -52,25 +58,28 @@ def main(argv=None):
     from paper_1602_08735_amd import inputs, learned
 
     crit = learned.CRITERIA[args.criterion]
-    rule, ds = (1, True) if args.base == "largest-ds" else (0, False)
+    choice = args.base == "choice"
+    rule, ds = (1, True) if args.base in ("largest-ds", "choice") else (0, False)
+    n_out = 2 if choice else 5
     rng = np.random.default_rng(args.seed)
     log = lambda s: print(f"[{time.strftime('%H:%M:%S')}] {s}", flush=True)
     t0 = time.time()
     tb = inputs.config5_train(n_instances=args.instances, m=args.m)
     db = V.DeviceBatch(tb)
-    nd = learned.plain_decisions(db, crit, type_rule=rule)
+    nd = (learned.choice_decisions(db, crit) if choice
+          else learned.plain_decisions(db, crit, type_rule=rule))
     src, d = learned.sample_decisions(nd, args.per_instance, rng)
     log(f"{len(src)} decisions sampled from {args.instances} instances")
     t1 = time.time()
-    x, info = learned.decision_features(db, crit, src, d, type_rule=rule)
+    x, info = learned.decision_features(db, crit, src, d, type_rule=rule, choice=choice)
     torch.cuda.synchronize()
     t2 = time.time()
-    labels, vals = learned.lookahead_labels(db, crit, src, d, info, 5, type_rule=rule,
-                                            downsize=ds, values=True)
+    labels, vals = learned.lookahead_labels(db, crit, src, d, info, n_out, type_rule=rule,
+                                            downsize=ds, values=True, choice=choice)
     if args.min_gain > 0:
         # the base choice: type 0 under the largest-type rule, else the smallest fit
         base = torch.zeros_like(labels) if rule == 1 else info[:, 1].contiguous()
-        v = vals.view(-1, 5)
+        v = vals.view(-1, n_out)
         v_base = v.gather(1, base.long().view(-1, 1)).view(-1)
         v_lab = v.gather(1, labels.long().view(-1, 1)).view(-1)
         labels = torch.where(v_base - v_lab >= args.min_gain, labels, base)
@@ -78,12 +87,12 @@ def main(argv=None):
     t3 = time.time()
     lab_np = labels.cpu().numpy()
     info_np = info.cpu().numpy()
-    dist = np.bincount(lab_np, minlength=5)
+    dist = np.bincount(lab_np, minlength=n_out)
     agree = float(np.mean(lab_np == (0 if rule == 1 else info_np[:, 1])))
-    log(f"features {t2 - t1:.2f}s, labels {t3 - t2:.2f}s ({25 * len(src)} rollouts); "
+    log(f"features {t2 - t1:.2f}s, labels {t3 - t2:.2f}s ({n_out * n_out * len(src)} rollouts); "
         f"label histogram {dist.tolist()}, equal to the plain choice {agree:.3f}")
     mask = info[:, 0].contiguous()
-    tr, losses = learned.train(x, mask, labels, 5, epochs=args.epochs, batch=args.batch,
+    tr, losses = learned.train(x, mask, labels, n_out, epochs=args.epochs, batch=args.batch,
                                lr=args.lr, rng=rng, log=log)
     t4 = time.time()
     model = tr.export()
@@ -92,13 +101,13 @@ def main(argv=None):
         f.write(bytes(model))
     eb = inputs.config5_eval(n_instances=args.eval_instances, m=args.eval_m)
     edb = V.DeviceBatch(eb)
-    res = learned.evaluate(edb, crit, tr.device_model, type_rule=rule, downsize=ds)
+    res = learned.evaluate(edb, crit, tr.device_model, type_rule=rule, downsize=ds, choice=choice)
     t5 = time.time()
     summary = {
         "criterion": args.criterion,
         "base": args.base, "min_gain": args.min_gain,
         "train_instances": args.instances, "train_m": args.m,
-        "decisions": int(len(src)), "rollouts": int(25 * len(src)),
+        "decisions": int(len(src)), "rollouts": int(n_out * n_out * len(src)),
         "label_histogram": dist.tolist(), "labels_equal_plain_choice": agree,
         "loss_first_last": [losses[0], losses[-1]],
         "seconds": {"features": t2 - t1, "labels": t3 - t2, "train": t4 - t3,
