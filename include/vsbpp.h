@@ -287,6 +287,26 @@ int32_t vsbpp_plan_launch(const vsbpp_plan* plan, vsbpp_launch* out);
 /* Releases the plan, its workspace and graph (after outstanding runs). */
 void vsbpp_plan_destroy(vsbpp_plan* plan);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one run of
+ * a device batch with a chosen launch shape, as a plan created with that
+ * shape would run it, but with no plan and no allocation of any kind.  The
+ * work counter of persistent launches (mode 1) and the largest-first
+ * schedule (lpt 1) live in one device array inside the library, a copy per
+ * GPU held until the process ends: 1 + 8192 int32 (32 KiB + 4 B), so lpt 1
+ * takes at most 8192 instances (more: VSBPP_E_SIZE).  Plain FF/BF/WF runs
+ * whose bins do not fit LDS need a plan's device region and return
+ * VSBPP_E_SIZE here, as from vsbpp_pack_batch.  `launch` may be NULL (the
+ * default shape).  The learned rules take a model and are not run here
+ * (VSBPP_E_MODEL).  Every call on one GPU uses that GPU's array: the counter
+ * is reset by a kernel on hip_stream before each run, and calls that overlap
+ * on one GPU (other streams or threads) race.  Asynchronous on hip_stream;
+ * returns VSBPP_OK or the codes of vsbpp_plan_create in its order of checks
+ * (nothing is launched on error). */
+int32_t vsbpp_pack_batch_static(const vsbpp_batch* batch, int32_t heuristic,
+                                const vsbpp_options* opt, const vsbpp_launch* launch,
+                                void* hip_stream);
+
 /* Exact optimum of every instance of a device-resident batch with at most
  * 12 items per instance (batch->max_items <= 12), for measuring heuristic
  * and learned packings against the optimum.  The cost of a packing is the

@@ -37,6 +37,7 @@ EXPORTS = (
     "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
     "vsbpp_plan_create_ex", "vsbpp_exact_batch", "vsbpp_cost", "vsbpp_lower_bound",
     "vsbpp_model_load", "vsbpp_model_free", "vsbpp_measure_peaks",
+    "vsbpp_pack_batch_static",
 )
 
 
@@ -396,6 +397,43 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def pack_batch_static(db: DeviceBatch, heuristic, *, launch: dict | None = None, stream=None,
+                      seed: int = 0, s1: int = 10, s2: int = 5,
+                      type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
+                      use_order: bool = True, use_seeds: bool = True,
+                      active_limit: int = 0, downsize: bool = False) -> None:
+    """One run of the batch with a launch shape, its work counter and schedule
+    in the library's own device array (vsbpp_pack_batch_static): allocates
+    nothing.  Runs that overlap on one GPU share that array and race."""
+    import torch
+
+    L = lib()
+    if not getattr(L, "_static_ready", False):
+        L.vsbpp_pack_batch_static.restype = ctypes.c_int32
+        L.vsbpp_pack_batch_static.argtypes = [ctypes.POINTER(_BatchDesc), ctypes.c_int32,
+                                              ctypes.POINTER(Options), ctypes.POINTER(Launch),
+                                              ctypes.c_void_p]
+        L._static_ready = True
+    ptr = lambda x: None if x is None else x.data_ptr()
+    desc = _BatchDesc(
+        db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
+        ptr(db.order) if use_order else None, ptr(db.seeds) if use_seeds else None,
+        db.max_items, db.max_types, db.max_cap,
+        ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize, 0)
+    lp = None
+    if launch is not None:
+        lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
+                    launch.get("waves_per_block", 4), launch.get("block_threads", 256),
+                    launch.get("lanes_per_instance", 64))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = L.vsbpp_pack_batch_static(ctypes.byref(desc), _heur(heuristic), ctypes.byref(o),
+                                   ctypes.byref(lp) if lp is not None else None,
+                                   ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise VsbppError(rc, "vsbpp_pack_batch_static")
 
 
 # ---------------------------------------------------------------------------
