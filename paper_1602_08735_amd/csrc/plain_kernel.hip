@@ -404,6 +404,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     int32_t thr_lane = 0x7FFFFFFF;
     float xcap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float inv_cap_lane = 0.0f;
+    // 1/B_1 and 1/m of the decision features, once per instance
+    float inv_b1 = 0.0f, inv_m = 0.0f;
     if constexpr (EXT) {
       if (a.force) {
         fd = uniform(a.force[3 * (int64_t)inst]);
@@ -417,7 +419,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       if (lane < 8) hist[lane] = 0;
       // features that are constants of the instance: B_2..B_5 over B_1, and
       // lane k's 1/B_k for the fill of the smallest fitting type
-      const float inv_b1 = 1.0f / (float)B1;
+      inv_b1 = uniform_f(1.0f / (float)B1);
+      inv_m = uniform_f(1.0f / (float)m);
 #pragma unroll
       for (int k = 1; k <= 4; ++k)
         xcap[k - 1] = k < n ? (float)readlane(cap_lane, k) * inv_b1 : 0.0f;
@@ -545,8 +548,6 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           const int64_t rsum = total - (int64_t)placed - w;
           int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
           after = min(after, next_min);
-          const float inv_b1 = 1.0f / (float)B1;
-          const float inv_m = 1.0f / (float)m;
           x[0] = (float)w * inv_b1;
           x[1] = (float)rem * inv_m;
           // with 32-bit keys m <= 65535 and B_1 <= 32767, so the remaining
@@ -582,7 +583,6 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
               const bool dump = d == fd && (a.feat_out || a.info_out);
               bool open = false;
               if (a.choice_rule == 2 || dump) {
-                const float inv_b1 = 1.0f / (float)B1;
                 const int32_t cb = readlane(cap_lane, (int)__popcll(hb) - 1);
                 const int32_t ca = readlane(cap_lane, (int)__popcll(ha) - 1);
                 const int32_t cw = readlane(cap_lane, (int)__popcll(ballot(cap_lane >= w)) - 1);
