@@ -735,7 +735,7 @@ k_h2s(BatchArgs a, int nbslots, int group) {
   // x = (W10 ^ nm) + ad: {s, nm, ad, mask}, one 16-byte read per placement
   __shared__ __align__(16) uint32_t s_keyc[4 * 3];
   // per bin type k: {B_k, the word of an empty bin of type k in slot 0
-  // (B_k << 10 | k), floor(B_k / 2), 0}
+  // (B_k << 10 | k), (floor(B_k / 2) + 1) << 10, 0}
   __shared__ __align__(16) int4 s_type[kMaxTypes];
   __shared__ uint32_t s_wmin[16];
   __shared__ int s_flag;
@@ -745,9 +745,10 @@ k_h2s(BatchArgs a, int nbslots, int group) {
   int32_t* arrA = reinterpret_cast<int32_t*>(smem);
   int32_t* tmplA = arrA + (size_t)nbslots * B;  // [nbslots]
   int32_t* s_ci = tmplA + nbslots;              // [B] chunk items
-  int32_t* s_cw = s_ci + B;                     // [B] chunk weights
-  int32_t* s_ct = s_cw + B;                     // [B] type of a new bin
-  int32_t* s_u = s_ct + B;                      // [spr] used bins
+  // [B] per chunk position: {w << 10, type of the bin the item opens when
+  // nothing fits}, one 8-byte read per placement
+  int2* s_cwt = reinterpret_cast<int2*>(s_ci + B);
+  int32_t* s_u = s_ci + 3 * B;                  // [spr] used bins
   int32_t* s_cst = s_u + spr;                   // [spr] subset cost
   int32_t* myA = arrA + ((tid >> 6) * nbslots) * 64 + (tid & 63);
   const int g = tid / group, r = tid - g * group;
@@ -788,7 +789,9 @@ k_h2s(BatchArgs a, int nbslots, int group) {
       const int32_t room = tid < n ? s_caps[tid] : 0;
       tmplA[tid] = (room << 10) | (tid << 5) | (tid < n ? tid : 0);
     }
-    if (tid < n) s_type[tid] = make_int4(s_caps[tid], (s_caps[tid] << 10) | tid, s_caps[tid] >> 1, 0);
+    if (tid < n)
+      s_type[tid] = make_int4(s_caps[tid], (s_caps[tid] << 10) | tid,
+                              ((s_caps[tid] >> 1) + 1) << 10, 0);
     const uint64_t seed = inst_seed(a, inst);
     Rule1Perm perm;
     perm.init(seed, (uint32_t)m);
@@ -812,13 +815,12 @@ k_h2s(BatchArgs a, int nbslots, int group) {
           const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
           const int32_t w = a.w[off + item];
           s_ci[tid] = item;
-          s_cw[tid] = w;
           // the bin this item opens when nothing fits: the smallest capacity
           // >= w (the capacities decrease, so the last of those), or B_1
           int t = 0;
           if (a.type_rule != 1)
             for (int kk = 1; kk < n; ++kk) t += s_caps[kk] >= w ? 1 : 0;
-          s_ct[tid] = t;
+          s_cwt[tid] = make_int2(w << 10, t);
         }
         __syncthreads();
       }
@@ -829,11 +831,11 @@ k_h2s(BatchArgs a, int nbslots, int group) {
       const bool active = k > 0 && r < kf;
       const int lq = q0 - cq;  // the subset's first position in the chunk
       uint32_t key = 0xFFFFFFFFu;
-      uint32_t used = 0, locs = 0;
+      uint32_t used = 0, locs = 0, pmv = 0;
       int32_t cost = 0;
       if (active) {
         // bins not used yet and bins not divided yet, one bit per slot
-        uint32_t nused = 0xFFFFFFFFu, nodiv = 0xFFFFFFFFu;
+        uint32_t nused = 0xFFFFFFFFu;
         for (int gi = 0; gi < (nbslots >> 2); ++gi) {
           const int4 tv = *reinterpret_cast<const int4*>(tmplA + 4 * gi);
           int32_t* const p = myA + 256 * gi;
@@ -843,6 +845,7 @@ k_h2s(BatchArgs a, int nbslots, int group) {
           p[192] = tv.w;
         }
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
+        pmv = pm;
         // A forced criterion c runs the same digit iteration from a word
         // whose every digit is c: 0, 2^31 (3 * 2^31 = 2^32 + 2^31) and
         // 2^32 - 1 (its deficit from 2^32 triples per step and stays below
@@ -851,10 +854,15 @@ k_h2s(BatchArgs a, int nbslots, int group) {
                           ? (a.force_crit == 0 ? 0u : (a.force_crit == 1 ? 0x80000000u : 0xFFFFFFFFu))
                           : digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
         int nb = n;
+        // the most bins any packer of the wave holds (wave-uniform; every
+        // packer starts with the n Rule-2 bins)
+        int nbw = n;
+        int sh = 0;
         for (int t = 0; t < k; ++t) {
           const int d = (pm >> (4 * t)) & 0xF;
-          const int32_t w = s_cw[lq + d];
-          const int32_t tn = s_ct[lq + d];
+          const int2 wt = s_cwt[lq + d];
+          const uint32_t W10 = (uint32_t)wt.x;  // w << 10
+          const int32_t tn = wt.y;
           // the criterion digit floor(3u / 2^32) times 16, the byte offset of
           // its key constants: floor(48u / 2^32) with the low four bits cleared
           const uint32_t koff = __umulhi(cu, 48u) & 0x30u;
@@ -863,10 +871,10 @@ k_h2s(BatchArgs a, int nbslots, int group) {
           const uint4 kc = *reinterpret_cast<const uint4*>(
               reinterpret_cast<const unsigned char*>(s_keyc) + koff);
           const uint32_t sx = kc.x;
-          const uint32_t x = (((uint32_t)w << 10) ^ kc.y) + kc.z;
+          const uint32_t x = (W10 ^ kc.y) + kc.z;
           const uint32_t msk = kc.w;
-          // groups that can hold bins after t placements (each adds <= 2)
-          const int ng = (min(nbslots, n + 2 * t) + 3) >> 2;
+          // groups that hold a bin of some packer of the wave
+          const int ng = (min(nbslots, nbw) + 3) >> 2;
           // two groups per LDS round trip, then an odd last group alone
           uint32_t best = 0xFFFFFFFFu;
           int gi = 0;
@@ -905,7 +913,7 @@ k_h2s(BatchArgs a, int nbslots, int group) {
           // the bin's word after the item: the chosen bin's, or an empty bin
           // of the item's type in slot b, with the room lowered by w (it
           // fits, so the low fields are untouched)
-          const int32_t nw = (found ? word : (ty.y | (b << 5))) - (w << 10);
+          const int32_t nw = (found ? word : (ty.y | (b << 5))) - (int32_t)W10;
           *pb = nw;
           nb += found ? 0 : 1;
           // a bin's first item adds its capacity to the cost (bit b of nused
@@ -914,15 +922,25 @@ k_h2s(BatchArgs a, int nbslots, int group) {
           nused &= ~(1u << b);
           // Rule 5: a bin at least half full (2 room <= cap, i.e. room <=
           // floor(cap / 2)) divides once, adding an empty bin of its type at
-          // the next free slot.  Without a division that slot is rewritten
-          // with the empty word it already holds (room 0, type 0), which no
-          // scan picks.
-          const bool split = ((nodiv >> b) & 1u) && (nw >> 10) <= ty.z;
-          nodiv &= split ? ~(1u << b) : 0xFFFFFFFFu;
+          // the next free slot.  Rooms only fall, so a bin divides at the
+          // one placement that takes its room from above floor(cap / 2) to
+          // at most that: the word before it (nw + W10, whose room field is
+          // the room before) is at least H = (floor(cap / 2) + 1) << 10 and
+          // the word after it is below H.  Every bin starts with room cap >
+          // floor(cap / 2).  Without a division the slot after the last bin
+          // is rewritten with the empty word it already holds (room 0, type
+          // 0), which no scan picks.
+          const uint32_t H = (uint32_t)ty.z;
+          const bool split = (uint32_t)nw < H && (uint32_t)nw + W10 >= H;
           const int nbn = nb;
           nb += split ? 1 : 0;
           *slot_at(myA, nbn) = (split ? ty.y : 0) | (nbn << 5);
-          locs |= (uint32_t)b << (5 * d);
+          // the bin of placement t, 5 bits at 5t
+          locs |= (uint32_t)b << sh;
+          sh += 5;
+          // a placement adds at most two bins to a packer
+          if (ballot(nb > nbw)) ++nbw;
+          if (ballot(nb > nbw)) ++nbw;
         }
         used = ~nused;
         key = ((uint32_t)cost << 10) | (uint32_t)r;
@@ -953,15 +971,17 @@ k_h2s(BatchArgs a, int nbslots, int group) {
       }
       carry += total;
       cost_acc += round_cost;
-      // the winner's wave writes its result: lane d the item at subset
-      // position d, lane b the type of bin slot b if used
+      // the winner's wave writes its result: lane t the item of placement
+      // t, lane b the type of bin slot b if used
       const int wr = (int)(gm & 1023u);  // the winning rank
       if (k > 0 && wave == g * wpg + (wr >> 6)) {
         const uint32_t wused = readlane(used, wr & 63);
         const uint32_t wlocs = readlane(locs, wr & 63);
+        const uint32_t wpm = readlane(pmv, wr & 63);
         if (lane < k) {
           const int b = (int)((wlocs >> (5 * lane)) & 31u);
-          a.assign[off + s_ci[lq + lane]] = before + (int)__popc(wused & ((1u << b) - 1u));
+          const int d = (int)((wpm >> (4 * lane)) & 0xFu);
+          a.assign[off + s_ci[lq + d]] = before + (int)__popc(wused & ((1u << b) - 1u));
         }
         if (lane < 32 && ((wused >> lane) & 1u)) {
           a.types[off + before + (int)__popc(wused & ((1u << lane) - 1u))] =

@@ -9,6 +9,11 @@
 * The Worst Fit key of the one-word bin encoding, (A ^ ~1023) + XW with
   XW = (32767 + w - (2^22 - 1)) << 10, equals (32767 - room + w) << 10 | tag
   and is below 2^25 exactly when the item fits.
+* Rule 5 in the second heuristic's kernel: with H = (floor(cap/2) + 1) << 10,
+  a bin divides at the placement whose bin word before it is >= H and after
+  it is < H.  Since rooms only fall, that is the one placement at which the
+  bin's load first reaches half its capacity, the division the oracle
+  records with an explicit mark.
 """
 import numpy as np
 
@@ -57,3 +62,26 @@ def test_worst_fit_key_of_one_word_bins():
         key = ((a ^ 0xFFFFFC00) + xw) & M32
         assert key == ((r5 - room + w) << 10) | tag
         assert (key < (1 << 25)) == (w <= room)
+
+
+def test_rule5_crossing_test_equals_the_divided_mark():
+    rng = np.random.default_rng(8)
+    for _ in range(4000):
+        cap = int(rng.integers(1, 32768))
+        tag = int(rng.integers(0, 1024))
+        h = ((cap >> 1) + 1) << 10
+        load, divided = 0, False
+        word = (cap << 10) | tag          # an empty bin: room = cap
+        while True:
+            room = cap - load
+            if room < 1:
+                break
+            w = int(rng.integers(1, room + 1))
+            after = word - (w << 10)      # the kernel's new word
+            kernel_split = after < h and after + (w << 10) >= h
+            load += w
+            oracle_split = (not divided) and 2 * load >= cap
+            divided = divided or oracle_split
+            assert kernel_split == oracle_split, (cap, load, w)
+            assert after == ((cap - load) << 10) | tag
+            word = after
