@@ -84,6 +84,7 @@ class _Opts(ctypes.Structure):
         ("downsize", ctypes.c_int32),
         ("criterion_rule", ctypes.c_int32),
         ("choice_rule", ctypes.c_int32),
+        ("rule2_order", ctypes.c_int32),
     ]
 
 
@@ -200,7 +201,8 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
          type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
          order=None, model: "Model | None" = None, force_event: int = -1,
          force_types=(0, 0), trace: bool = False, active_limit: int = 0,
-         downsize: bool = False, criterion_rule: int = 0, choice_rule: int = 0) -> Packing:
+         downsize: bool = False, criterion_rule: int = 0, choice_rule: int = 0,
+         rule2_order: int = 0) -> Packing:
     w = _i32(weights)
     c = _i32(caps)
     m = int(w.size)
@@ -217,6 +219,7 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     o.downsize = int(downsize)
     o.criterion_rule = int(criterion_rule)
     o.choice_rule = int(choice_rule)
+    o.rule2_order = int(rule2_order)
     tr_arr = None
     tr_count = ctypes.c_int32(0)
     if trace:

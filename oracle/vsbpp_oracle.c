@@ -116,6 +116,14 @@ static void pk_push(opacker* p, int32_t type) {
   p->nb++;
 }
 
+/* Rule 2 (Section 6.3): a packer starts with one empty bin of every type.
+ * The paper gives no order for them; it matters to First Fit (lowest index)
+ * and to ties.  order 0 creates them in type order (B_1 first), order 1 in
+ * increasing capacity (B_n first). */
+static void rule2_bins(opacker* p, int32_t n, int32_t order) {
+  for (int32_t ty = 0; ty < n; ++ty) pk_push(p, order ? n - 1 - ty : ty);
+}
+
 /* Type of a bin opened when no open bin can take the item.  The paper says
  * extra rules are needed to choose among bin types (Section 1) but gives
  * none.  SMALLEST_FIT takes the smallest capacity >= w; LARGEST takes B_1. */
@@ -262,6 +270,8 @@ static int32_t validate(const int32_t* w, int32_t m, const int32_t* caps, int32_
     if (o->downsize != 0 && o->downsize != 1) return ORC_E_OPTION;
     if (o->criterion_rule != 0 && o->criterion_rule != 1) return ORC_E_OPTION;
     if (o->choice_rule < 0 || o->choice_rule > 2) return ORC_E_OPTION;
+    if (o->rule2_order < 0 || o->rule2_order > 1 || (o->rule2_order == 1 && heuristic <= ORC_WF))
+      return ORC_E_OPTION;
     if (o->choice_rule > 0 &&
         (heuristic > ORC_WF || o->type_rule != ORC_TYPE_LARGEST || o->downsize != 1 ||
          o->active_limit != 0))
@@ -560,7 +570,7 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
   orc_decision* tr = (orc_decision*)malloc(sizeof(orc_decision) * (size_t)(d + 1));
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize, 0, 0};
+  orc_opts o = {0, 10, 5, type_rule, -1, NULL, NULL, -1, 0, 0, tr, d + 1, &count, 0, downsize, 0, 0, 0};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label = -1;
   if (rc >= 0 && d < count) {
@@ -572,7 +582,7 @@ int32_t orc_rollout_label_ex(const int32_t* w, int32_t m, const int32_t* caps, i
       if (!((feasible >> k1) & 1u)) continue;
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < n; ++k2) {
-        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize, 0, 0};
+        orc_opts f = {0, 10, 5, type_rule, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, downsize, 0, 0, 0};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }
@@ -602,14 +612,14 @@ int32_t orc_choice_label(const int32_t* w, int32_t m, const int32_t* caps, int32
   int32_t* types = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
   int32_t count = 0;
   int64_t cost = 0;
-  orc_opts o = {0, 10, 5, ORC_TYPE_LARGEST, -1, NULL, NULL, -1, 0, 0, NULL, 0, &count, 0, 1, 0, 1};
+  orc_opts o = {0, 10, 5, ORC_TYPE_LARGEST, -1, NULL, NULL, -1, 0, 0, NULL, 0, &count, 0, 1, 0, 1, 0};
   int32_t rc = orc_pack(w, m, caps, n, crit, &o, assign, types, &cost, NULL);
   int32_t label;
   if (rc >= 0 && d < count) {
     for (int32_t k1 = 0; k1 < 2; ++k1) {
       int64_t v = -1;
       for (int32_t k2 = 0; k2 < 2; ++k2) {
-        orc_opts f = {0, 10, 5, ORC_TYPE_LARGEST, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, 1, 0, 1};
+        orc_opts f = {0, 10, 5, ORC_TYPE_LARGEST, -1, NULL, NULL, d, k1, k2, NULL, 0, NULL, 0, 1, 0, 1, 0};
         orc_pack(w, m, caps, n, crit, &f, assign, types, &cost, NULL);
         if (v < 0 || cost < v) v = cost;
       }
@@ -709,7 +719,7 @@ static int32_t run_h1(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
     }
     opacker p;
     pk_init(&p);
-    for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty); /* Rule 2 */
+    rule2_bins(&p, n, o->rule2_order);
     for (int32_t t = 0; t < k; ++t) {
       int32_t c = o->force_crit >= 0 ? o->force_crit
                                      : orc_criterion(ck, (uint64_t)(q0 + t));
@@ -781,7 +791,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
       }
       opacker p;
       pk_init(&p);
-      for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
+      rule2_bins(&p, n, o->rule2_order);
       for (int32_t t = 0; t < k; ++t) {
         int32_t c = o->force_crit >= 0
                         ? o->force_crit
@@ -801,7 +811,7 @@ static int32_t run_h2(const int32_t* w, int32_t m, const int32_t* caps, int32_t 
     nth_permutation(best_r, k, order);
     opacker p;
     pk_init(&p);
-    for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
+    rule2_bins(&p, n, o->rule2_order);
     for (int32_t t = 0; t < k; ++t) {
       int32_t c = o->force_crit >= 0
                       ? o->force_crit
@@ -852,7 +862,7 @@ int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
 static int32_t orc_pack_run(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                             int32_t heuristic, const orc_opts* opt, int32_t* assign,
                             int32_t* types, int64_t* cost, orc_stats* stats) {
-  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0, 0, 0};
+  orc_opts def = {0, 10, 5, ORC_TYPE_SMALLEST_FIT, -1, NULL, NULL, -1, 0, 0, NULL, 0, NULL, 0, 0, 0, 0, 0};
   const orc_opts* o = opt ? opt : &def;
   if (!assign || !types || !cost) return ORC_E_NULL;
   int32_t rc = validate(w, m, caps, n, heuristic, o);
@@ -883,8 +893,12 @@ int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
   int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
   opacker p;
   pk_init(&p);
-  if (rule2)
-    for (int32_t ty = 0; ty < n; ++ty) pk_push(&p, ty);
+  if (rule2 < 0 || rule2 > 2) {
+    free(items);
+    free(local);
+    return ORC_E_OPTION;
+  }
+  if (rule2) rule2_bins(&p, n, rule2 - 1);
   for (int32_t t = 0; t < m; ++t) {
     items[t] = t;
     local[t] = place(&p, caps, n, w[t], crit[t], rule5, type_rule, 0, 0, NULL, NULL, NULL, NULL);

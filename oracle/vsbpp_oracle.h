@@ -91,6 +91,9 @@ typedef struct {
                              model (n_out >= 2) chooses at each contested
                              placement between the criterion's bin (output
                              0) and a new bin (output 1)                    */
+  int32_t rule2_order;    /* H1/H2: order of Rule 2's empty bins in the
+                             packer, 0 = B_1 first (type order), 1 = B_n
+                             first (increasing capacity); plain: must be 0  */
 } orc_opts;
 
 typedef struct {
@@ -122,8 +125,8 @@ int32_t orc_pack(const int32_t* w, int32_t m, const int32_t* caps, int32_t n,
                  int32_t* types, int64_t* cost, orc_stats* stats);
 
 /* One packer of the hybrid P system with explicit per-placement criteria:
- * Rule-2 bins (one empty bin per type) when rule2 != 0, Rule-5 division when
- * rule5 != 0.  Items are placed in the given order.  Same outputs as
+ * Rule-2 bins (one empty bin per type: B_1 first when rule2 == 1, B_n first
+ * when rule2 == 2) when rule2 != 0, Rule-5 division when rule5 != 0.  Items are placed in the given order.  Same outputs as
  * orc_pack (used bins only, creation order). */
 int32_t orc_pack_packer(const int32_t* w, int32_t m, const int32_t* caps,
                         int32_t n, const int32_t* crit, int32_t rule2,

@@ -121,6 +121,40 @@ def test_hand_example_D_rules_2_and_5(orc):
     assert r.cost == e["cost"]
 
 
+def test_hand_example_D_ascending_rule2_order(orc):
+    e = golden("hand_examples.json")["D_ascending"]
+    r = orc.pack_packer(e["w"], e["caps"], e["crit"], rule2=2, rule5=True)
+    assert r.assignment.tolist() == e["assignment"]
+    assert r.bin_types.tolist() == e["types"]
+    assert r.cost == e["cost"]
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_rule2_order_in_the_heuristics(orc, order):
+    """H1 with one sublist (s1 = m, identity order, a forced criterion) is
+    the single packer of pack_packer with that Rule-2 order; H2 with one
+    subset and a forced criterion is the cheapest of its k! packers."""
+    import itertools
+
+    rng = np.random.default_rng(40 + order)
+    for _ in range(60):
+        w, caps = inputs.random_small(rng, m_max=6, n_max=4, b1_max=40)
+        m = w.size
+        for c in (0, 1, 2):
+            r = orc.pack(w, caps, "H1", s1=m, order=np.arange(m), force_crit=c,
+                         rule2_order=order)
+            p = orc.pack_packer(w, caps, [c] * m, rule2=1 + order, rule5=True)
+            assert r.cost == p.cost and r.assignment.tolist() == p.assignment.tolist()
+            r2 = orc.pack(w, caps, "H2", s2=m, order=np.arange(m), force_crit=c,
+                          rule2_order=order)
+            best = min(orc.pack_packer(w[list(pi)], caps, [c] * m, rule2=1 + order,
+                                       rule5=True).cost
+                       for pi in itertools.permutations(range(m)))
+            assert r2.cost == best
+    with pytest.raises(orc.OracleError):
+        orc.pack([3, 4], [10, 6], "BF", rule2_order=1)
+
+
 def test_hand_example_E_second_heuristic(orc):
     e = golden("hand_examples.json")["E"]
     r = orc.pack(e["w"], e["caps"], "H2", force_crit=1, order=e["order"])
