@@ -144,6 +144,12 @@ typedef struct vsbpp_options {
                                bin choice below).  2 needs a model, so only
                                vsbpp_pack_batch_ex and vsbpp_plan_create_ex
                                take it (the other calls: VSBPP_E_MODEL).     */
+  int32_t rule2_order;      /* H1/H2: the order in which Rule 2 creates a
+                               packer's empty bins (Section 6.3 gives none; it
+                               decides First Fit's lowest index and ties):
+                               0 (default) type order, B_1 first; 1
+                               increasing capacity, B_n first.  Nonzero with
+                               plain FF/BF/WF: VSBPP_E_OPTION.                */
 } vsbpp_options;
 
 void vsbpp_options_init(vsbpp_options* opt);

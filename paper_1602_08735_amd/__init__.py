@@ -63,6 +63,7 @@ class Options(ctypes.Structure):
         ("downsize", ctypes.c_int32),
         ("criterion_rule", ctypes.c_int32),
         ("choice_rule", ctypes.c_int32),
+        ("rule2_order", ctypes.c_int32),
     ]
 
 
@@ -111,7 +112,7 @@ def lib():
 
 def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT,
             force_crit: int = -1, active_limit: int = 0, downsize: bool = False,
-            criterion_rule: int = 0, choice_rule: int = 0) -> Options:
+            criterion_rule: int = 0, choice_rule: int = 0, rule2_order: int = 0) -> Options:
     o = Options()
     lib().vsbpp_options_init(ctypes.byref(o))
     o.seed = seed & (2**64 - 1)
@@ -123,6 +124,7 @@ def options(seed: int = 0, s1: int = 10, s2: int = 5, type_rule: int = TYPE_SMAL
     o.downsize = int(downsize)
     o.criterion_rule = int(criterion_rule)
     o.choice_rule = int(choice_rule)
+    o.rule2_order = int(rule2_order)
     return o
 
 
@@ -206,7 +208,7 @@ def _heur(h) -> int:
 
 def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
          type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, order=None,
-         active_limit: int = 0, downsize: bool = False) -> Packing:
+         active_limit: int = 0, downsize: bool = False, rule2_order: int = 0) -> Packing:
     """One instance through vsbpp_pack_ex (host arrays, synchronous)."""
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.int32))
     c = np.ascontiguousarray(np.asarray(caps, dtype=np.int32))
@@ -214,7 +216,8 @@ def pack(weights, caps, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
     a = np.zeros(max(m, 1), dtype=np.int32)
     t = np.zeros(max(m, 1), dtype=np.int32)
     cost = ctypes.c_int64(0)
-    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize)
+    o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize,
+                rule2_order=rule2_order)
     ordv = None
     if order is not None:
         ordv = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
@@ -259,14 +262,14 @@ class DeviceBatch:
 def pack_batch(db: DeviceBatch, heuristic, *, seed: int = 0, s1: int = 10, s2: int = 5,
                type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1, stream=None,
                use_order: bool = True, use_seeds: bool = True, active_limit: int = 0,
-               downsize: bool = False, choice_rule: int = 0) -> None:
+               downsize: bool = False, choice_rule: int = 0, rule2_order: int = 0) -> None:
     """Launches vsbpp_pack_batch on the given torch stream (default: current).
     Results land in db.assignment / db.bin_types / db.nbins / db.cost."""
     import torch
 
     s = stream if stream is not None else torch.cuda.current_stream()
     o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize,
-                choice_rule=choice_rule)
+                choice_rule=choice_rule, rule2_order=rule2_order)
     ptr = lambda x: None if x is None else x.data_ptr()
     rc = lib().vsbpp_pack_batch(
         db.n, ptr(db.weights), ptr(db.item_off), ptr(db.caps), ptr(db.cap_off),
@@ -339,7 +342,7 @@ class Plan:
                  s2: int = 5, type_rule: int = TYPE_SMALLEST_FIT, force_crit: int = -1,
                  use_order: bool = True, use_seeds: bool = True, model_ptr=None,
                  active_limit: int = 0, downsize: bool = False, criterion_rule: int = 0,
-                 choice_rule: int = 0):
+                 choice_rule: int = 0, rule2_order: int = 0):
         L = _plan_lib()
         ptr = lambda x: None if x is None else x.data_ptr()
         self.db = db
@@ -349,7 +352,7 @@ class Plan:
             db.max_items, db.max_types, db.max_cap,
             ptr(db.assignment), ptr(db.bin_types), ptr(db.nbins), ptr(db.cost))
         o = options(seed, s1, s2, type_rule, force_crit, active_limit, downsize, criterion_rule,
-                    choice_rule)
+                    choice_rule, rule2_order)
         lp = None
         if launch is not None:
             lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),

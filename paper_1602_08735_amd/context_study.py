@@ -32,10 +32,18 @@ PAPER_TABLE3 = {100: (1119, 1600, 2300), 200: (2171, 3800, 4300), 500: (5511, 99
                 10000: (105516, 226600, 200800), 50000: (526327, 1153900, 1009200),
                 100000: (1051854, 2308800, 2016200)}
 
-# (label, heuristic, use the entry's order, plan options)
+# (label, heuristic, use the entry's order, plan options).  The alternatives
+# the text leaves open for the hybrid heuristics: Rule 2's empty bins in type
+# order (B_1 first) or in increasing capacity ("asc"), and a used bin costing
+# its type's capacity or the smallest capacity holding its load ("+ds").
 RUNS = (("H1", "H1", False, {}),
+        ("H1 asc", "H1", False, {"rule2_order": 1}),
+        ("H1 +ds", "H1", False, {"downsize": True}),
+        ("H1 asc +ds", "H1", False, {"rule2_order": 1, "downsize": True}),
         ("H2", "H2", False, {}),
+        ("H2 asc", "H2", False, {"rule2_order": 1}),
         ("H2 +ds", "H2", False, {"downsize": True}),
+        ("H2 asc +ds", "H2", False, {"rule2_order": 1, "downsize": True}),
         ("BF", "BF", True, {}),
         ("BF largest +ds", "BF", True, {"type_rule": 1, "downsize": True}))
 

@@ -70,8 +70,9 @@ struct LanePacker {
     }
   }
 
-  // Rule 2: one empty bin per type; slots [n, nbslots) hold no bin.
-  __device__ void init(const int32_t* scaps, int n, int nbslots) {
+  // Rule 2: one empty bin per type, B_1 first (or B_n first with rev);
+  // slots [n, nbslots) hold no bin.
+  __device__ void init(const int32_t* scaps, int n, int nbslots, int rev) {
     for (int g = 0; g < (nbslots >> 2); ++g) {
       int4 r, c;
       int* rp = &r.x;
@@ -79,7 +80,7 @@ struct LanePacker {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int b = (g << 2) + j;
-        const int32_t v = b < n ? scaps[b] : 0;
+        const int32_t v = b < n ? scaps[rev ? n - 1 - b : b] : 0;
         if constexpr (kPacked) {
           rp[j] = (int32_t)(((uint32_t)v << 16) | (uint32_t)v);
         } else {
@@ -434,7 +435,7 @@ __global__ void __launch_bounds__(LC ? kH1LearnedMaxBlock : 1024) k_h1(BatchArgs
       const bool active = I < l;
       const int q0 = I * s1;
       const int k = active ? min(s1, m - q0) : 0;
-      if (active) pk.init(s_caps, n, nbslots);
+      if (active) pk.init(s_caps, n, nbslots, a.rule2_order);
       for (int t = 0; t < s1; ++t) {
         if (t < k) {
           const int q = q0 + t;
@@ -619,7 +620,7 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
       uint64_t u = 0;
       int64_t c = 0;
       if (active) {
-        pk.init(s_caps, n, nbslots);
+        pk.init(s_caps, n, nbslots, a.rule2_order);
         const uint32_t pm = k == S ? pm_full : nth_perm(r, k);
         uint32_t cu = digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
         for (int t = 0; t < k; ++t) {
@@ -784,10 +785,12 @@ k_h2s(BatchArgs a, int nbslots, int group) {
       __syncthreads();
       continue;
     }
-    // Rule 2 template: bins 0..n-1 empty with their capacity as room
+    // Rule 2 template: bins 0..n-1 empty with their capacity as room, in
+    // type order (B_1 first) or increasing capacity (B_n first)
     if (tid < nbslots) {
-      const int32_t room = tid < n ? s_caps[tid] : 0;
-      tmplA[tid] = (room << 10) | (tid << 5) | (tid < n ? tid : 0);
+      const int ty = a.rule2_order ? n - 1 - tid : tid;
+      const int32_t room = tid < n ? s_caps[ty] : 0;
+      tmplA[tid] = (room << 10) | (tid << 5) | (tid < n ? ty : 0);
     }
     if (tid < n)
       s_type[tid] = make_int4(s_caps[tid], (s_caps[tid] << 10) | tid,
@@ -824,10 +827,12 @@ k_h2s(BatchArgs a, int nbslots, int group) {
         }
         __syncthreads();
       }
-      const int I = base_I + g;
+      // a group is a whole number of wavefronts, so the subset, its size
+      // and its permutation count are wave-uniform
+      const int I = uniform(base_I + g);
       const int q0 = I * S;
-      const int k = I < l ? min(S, m - q0) : 0;
-      const int kf = factorial_small(k);
+      const int k = uniform(I < l ? min(S, m - q0) : 0);
+      const int kf = uniform(factorial_small(k));
       const bool active = k > 0 && r < kf;
       const int lq = q0 - cq;  // the subset's first position in the chunk
       uint32_t key = 0xFFFFFFFFu;

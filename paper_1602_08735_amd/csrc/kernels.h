@@ -35,6 +35,7 @@ struct BatchArgs {
   int32_t active_limit;     // plain FF/BF/WF: bins open at once (0: no limit)
   int32_t downsize;         // 1: a pass after packing gives every bin its smallest type
   int32_t criterion_rule;   // H1: 0 Rule 3's draw, 1 the model picks FF/BF/WF
+  int32_t rule2_order;      // H1/H2: Rule 2's empty bins B_1 first (0) or B_n first (1)
   int32_t choice_rule;      // plain FF/BF/WF (largest type, downsizing): 0 off, 1 contested
                             // placements are the decisions, 2 the model keeps or opens
   int32_t s1;               // H1 items per sublist

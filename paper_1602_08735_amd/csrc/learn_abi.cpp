@@ -114,6 +114,7 @@ int32_t vsbpp_pack_batch_ex(const vsbpp_batch* b, int32_t heuristic, const vsbpp
   a.downsize = o.downsize;
   a.criterion_rule = o.criterion_rule;
   a.choice_rule = o.choice_rule;
+  a.rule2_order = o.rule2_order;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   if (dec) {

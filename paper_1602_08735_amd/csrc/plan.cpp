@@ -259,6 +259,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
   a.downsize = o.downsize;
   a.criterion_rule = o.criterion_rule;
   a.choice_rule = o.choice_rule;
+  a.rule2_order = o.rule2_order;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   a.model = (learned || o.criterion_rule == 1 || o.choice_rule == 2) ? d_model : nullptr;

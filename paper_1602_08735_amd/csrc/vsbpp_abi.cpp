@@ -58,12 +58,14 @@ int32_t check_options(const vsbpp_options& o) {
   if (o.downsize != 0 && o.downsize != 1) return VSBPP_E_OPTION;
   if (o.criterion_rule != 0 && o.criterion_rule != 1) return VSBPP_E_OPTION;
   if (o.choice_rule < 0 || o.choice_rule > 2) return VSBPP_E_OPTION;
+  if (o.rule2_order < 0 || o.rule2_order > 1) return VSBPP_E_OPTION;
   return VSBPP_OK;
 }
 
 // options that only some heuristics take
 int32_t check_heuristic_options(const vsbpp_options& o, int32_t heuristic) {
   if (o.active_limit > 0 && heuristic > VSBPP_WF) return VSBPP_E_OPTION;
+  if (o.rule2_order != 0 && heuristic <= VSBPP_WF) return VSBPP_E_OPTION;  // no Rule 2
   if (o.criterion_rule == 1 && (heuristic != VSBPP_H1 || o.force_criterion != -1))
     return VSBPP_E_OPTION;
   // the bin choice compares bins by their downsized capacity: plain rules,
@@ -327,6 +329,7 @@ BatchArgs batch_args(const vsbpp_batch& b, const vsbpp_options& o) {
   a.downsize = o.downsize;
   a.criterion_rule = o.criterion_rule;
   a.choice_rule = o.choice_rule;
+  a.rule2_order = o.rule2_order;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   return a;
@@ -459,6 +462,7 @@ void vsbpp_options_init(vsbpp_options* opt) {
   opt->downsize = 0;
   opt->criterion_rule = 0;
   opt->choice_rule = 0;
+  opt->rule2_order = 0;
 }
 
 const char* vsbpp_strerror(int32_t code) {
@@ -539,6 +543,7 @@ int32_t vsbpp_pack_ex(const int32_t* weights, int32_t m, const int32_t* capaciti
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
+  a.rule2_order = o.rule2_order;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   DevBuf<unsigned char> dspill;
@@ -619,6 +624,7 @@ int32_t vsbpp_pack_batch(int32_t num_instances, const int32_t* d_weights,
   a.force_crit = o.force_criterion;
   a.active_limit = o.active_limit;
   a.downsize = o.downsize;
+  a.rule2_order = o.rule2_order;
   a.s1 = o.h1_items_per_sublist;
   a.s2 = o.h2_subset_size;
   return launch_batch(a, heuristic, (hipStream_t)hip_stream);
