@@ -259,6 +259,17 @@ typedef struct vsbpp_launch {
   int32_t waves_per_block;
   int32_t block_threads;
   int32_t lanes_per_instance;
+  int32_t waves_per_instance;  /* FF/BF/WF: 1 (0 means 1), or 2 or 4
+                                  wavefronts of one workgroup sharing one
+                                  instance's bins (its groups of 256 bin
+                                  positions dealt out among them; one barrier
+                                  per item), for instances of thousands of
+                                  items; only for runs with B_1 <= 32767, m <=
+                                  65535, no scorer, hooks or bound on the
+                                  open bins, whose bins fit one workgroup's
+                                  LDS, and with lanes_per_instance 64, else
+                                  VSBPP_E_OPTION.  waves_per_block is then
+                                  ignored. (Appended last.)                   */
 } vsbpp_launch;
 
 enum {

@@ -294,7 +294,7 @@ def best_of(cost_tensor, num: int, out_tensor, stream=None) -> None:
 class Launch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("lpt", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("lanes_per_instance", ctypes.c_int32)]
+                ("lanes_per_instance", ctypes.c_int32), ("waves_per_instance", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -357,7 +357,8 @@ class Plan:
         if launch is not None:
             lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
                         launch.get("waves_per_block", 4), launch.get("block_threads", 256),
-                        launch.get("lanes_per_instance", 64))
+                        launch.get("lanes_per_instance", 64),
+                        launch.get("waves_per_instance", 1))
         flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
         h = ctypes.c_void_p()
         if model_ptr is not None:
@@ -430,7 +431,8 @@ def pack_batch_static(db: DeviceBatch, heuristic, *, launch: dict | None = None,
     if launch is not None:
         lp = Launch(launch.get("mode", 0), launch.get("lpt", 0),
                     launch.get("waves_per_block", 4), launch.get("block_threads", 256),
-                    launch.get("lanes_per_instance", 64))
+                    launch.get("lanes_per_instance", 64),
+                    launch.get("waves_per_instance", 1))
     s = stream if stream is not None else torch.cuda.current_stream()
     rc = L.vsbpp_pack_batch_static(ctypes.byref(desc), _heur(heuristic), ctypes.byref(o),
                                    ctypes.byref(lp) if lp is not None else None,

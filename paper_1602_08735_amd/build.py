@@ -11,8 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvsbpp.so")
 SOURCES = ["vsbpp_abi.cpp", "plan.cpp", "learn_abi.cpp", "host_calls.cpp", "plain_kernel.hip", "plain_seg_kernel.hip", "hps_kernels.hip",
            "learn_kernels.hip", "bounds_kernel.hip", "exact_kernel.hip", "downsize_kernel.hip",
-           "peaks_kernel.hip", "static_run.hip"]
-HEADERS = ["device_common.h", "kernels.h", "host_internal.h", "learn.h"]
+           "peaks_kernel.hip", "static_run.hip", "plain_mw_kernel.hip"]
+HEADERS = ["device_common.h", "kernels.h", "host_internal.h", "learn.h", "plain_common.h",
+           "block_common.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -26,11 +26,15 @@ struct LaunchCfg {
   int block = 256;  // H1/H2 workgroup size
   int seg = 64;   // FF/BF/WF lanes per instance (64, or 16/32: several
                   // instances per wavefront)
+  int wpi = 1;    // FF/BF/WF wavefronts per instance (1, or 2/4 sharing one
+                  // instance's bins)
 };
 
 // Plain runs that the several-instances-per-wavefront kernel takes: 32-bit
 // keys, no scorer, decision hooks or bound on the open bins.
 bool seg_eligible(const BatchArgs& a, int heuristic);
+// Plain runs that the several-wavefronts-per-instance kernel takes.
+bool mw_eligible(const BatchArgs& a, int heuristic);
 
 // Shape-independent checks of a launch configuration for a batch; returns a
 // VSBPP_E_* code or 0.

@@ -146,6 +146,12 @@ size_t plain_seg_stride(int slots, int max_items);
 hipError_t launch_plain_seg(const BatchArgs& a, int crit, int seg, int wpb, size_t seg_stride,
                             int grid, hipStream_t s);
 int plain_seg_blocks_per_cu(int crit, int seg, int wpb, size_t seg_stride);
+// plain FF/BF/WF with wpi = 2 or 4 wavefronts per instance (one workgroup
+// each), 32-bit keys, no scorer, hooks, bound or device region; LDS bytes per
+// workgroup for a.slots key slots
+size_t plain_mw_lds(int slots, int max_items);
+hipError_t launch_plain_mw(const BatchArgs& a, int crit, int wpi, int grid, hipStream_t s);
+int plain_mw_blocks_per_cu(int crit, int wpi, size_t lds);
 hipError_t launch_h1_grid(const BatchArgs& a, bool wide, int nb_regs, int block_threads,
                           int grid, hipStream_t s);
 hipError_t launch_h2_grid(const BatchArgs& a, H2Kernel k, int nb_regs, int block_threads,

@@ -48,7 +48,7 @@ int bucket(long long x) {
 
 std::string tune_key(int heuristic, const vsbpp::BatchArgs& a) {
   std::ostringstream k;
-  k << "v2-h" << heuristic << (a.type_rule == 2 ? "L" : "") << (a.criterion_rule == 1 ? "C" : "")
+  k << "v3-h" << heuristic << (a.type_rule == 2 ? "L" : "") << (a.criterion_rule == 1 ? "C" : "")
     << (a.choice_rule == 2 ? "B" : "") << "-m" << bucket(a.max_items)
     << "-t" << a.max_types << "-c"
     << (a.max_cap > 0x7FFF ? 1 : 0) << "-n" << bucket(a.num) << "-s"
@@ -69,7 +69,7 @@ void load_cache_locked() {
   std::ifstream f(p);
   std::string key;
   vsbpp::LaunchCfg c;
-  while (f >> key >> c.mode >> c.lpt >> c.wpb >> c.block >> c.seg) g_tune[key] = c;
+  while (f >> key >> c.mode >> c.lpt >> c.wpb >> c.block >> c.seg >> c.wpi) g_tune[key] = c;
 }
 
 void store_cache_locked() {
@@ -78,7 +78,7 @@ void store_cache_locked() {
   std::ofstream f(p, std::ios::trunc);
   for (const auto& kv : g_tune)
     f << kv.first << " " << kv.second.mode << " " << kv.second.lpt << " " << kv.second.wpb << " "
-      << kv.second.block << " " << kv.second.seg << "\n";
+      << kv.second.block << " " << kv.second.seg << " " << kv.second.wpi << "\n";
 }
 
 int32_t run_eager(vsbpp_plan* p, hipStream_t s) {
@@ -159,6 +159,7 @@ int32_t autotune(vsbpp_plan* p, vsbpp::LaunchCfg* best) {
       for (const auto& tc : timed)
         if (tc.first <= it->first * 1.02f && tc.second.mode == best->mode &&
             tc.second.lpt == best->lpt && tc.second.seg == best->seg &&
+            tc.second.wpi == best->wpi &&
             tc.second.wpb > best->wpb)
           *best = tc.second;
     }
@@ -287,6 +288,7 @@ int32_t vsbpp_plan_create_ex(const vsbpp_batch* b, int32_t heuristic, const vsbp
     p->cfg.wpb = launch->waves_per_block;
     p->cfg.block = launch->block_threads;
     p->cfg.seg = launch->lanes_per_instance == 0 ? 64 : launch->lanes_per_instance;
+    p->cfg.wpi = launch->waves_per_instance == 0 ? 1 : launch->waves_per_instance;
     rc = vsbpp::check_cfg(p->cfg, heuristic, a);
   } else {
     const std::string key = tune_key(heuristic, a);
@@ -342,6 +344,7 @@ int32_t vsbpp_plan_launch(const vsbpp_plan* p, vsbpp_launch* out) {
   out->waves_per_block = p->cfg.wpb;
   out->block_threads = p->cfg.block;
   out->lanes_per_instance = p->cfg.seg;
+  out->waves_per_instance = p->cfg.wpi;
   return VSBPP_OK;
 }
 

@@ -71,6 +71,7 @@ extern "C" int32_t vsbpp_pack_batch_static(const vsbpp_batch* b, int32_t heurist
     c.wpb = launch->waves_per_block;
     c.block = launch->block_threads;
     c.seg = launch->lanes_per_instance == 0 ? 64 : launch->lanes_per_instance;
+    c.wpi = launch->waves_per_instance == 0 ? 1 : launch->waves_per_instance;
   }
   // the schedule holds at most kLptMax instances
   if (c.lpt == 1 && a.num > vsbpp::kLptMax) return VSBPP_E_SIZE;

@@ -210,6 +210,14 @@ SegShape seg_shape(const BatchArgs& a, int seg) {
 
 }  // namespace
 
+bool mw_eligible(const BatchArgs& a, int heuristic) {
+  if (heuristic > VSBPP_WF || is_wide(a) || plain_ext(a) || a.active_limit != 0 ||
+      a.max_items < 1)
+    return false;
+  const size_t lds = plain_mw_lds(round_up(a.max_items, 256), a.max_items);
+  return lds + 256 <= (size_t)device_info().max_lds_block;
+}
+
 bool seg_eligible(const BatchArgs& a, int heuristic) {
   return heuristic <= VSBPP_WF && !is_wide(a) && !plain_ext(a) && a.active_limit == 0 &&
          a.max_items >= 1 && (seg_shape(a, 16).max_wpb >= 1 || seg_shape(a, 32).max_wpb >= 1);
@@ -219,6 +227,8 @@ int32_t check_cfg(const LaunchCfg& c, int heuristic, const BatchArgs& a) {
   if (c.mode < 0 || c.mode > 1 || c.lpt < 0 || c.lpt > 1) return VSBPP_E_OPTION;
   if (c.lpt && a.num > kLptMax) return VSBPP_E_OPTION;
   if (c.seg != 64 && c.seg != 32 && c.seg != 16) return VSBPP_E_OPTION;
+  if (c.wpi != 1 && c.wpi != 2 && c.wpi != 4) return VSBPP_E_OPTION;
+  if (c.wpi != 1 && (c.seg != 64 || !mw_eligible(a, heuristic))) return VSBPP_E_OPTION;
   if (heuristic <= VSBPP_WF) {
     if (c.wpb < 1 || c.wpb > 8) return VSBPP_E_OPTION;
     if (c.seg != 64) {
@@ -260,6 +270,15 @@ std::vector<LaunchCfg> candidate_cfgs(int heuristic, const BatchArgs& a) {
           c.lpt = lpt;
           c.wpb = wpb;
           v.push_back(c);
+        }
+        if (mw_eligible(a, heuristic)) {
+          for (int wpi : {2, 4}) {
+            LaunchCfg c;
+            c.mode = mode;
+            c.lpt = lpt;
+            c.wpi = wpi;
+            v.push_back(c);
+          }
         }
         if (seg_eligible(a, heuristic)) {
           for (int seg : {16, 32}) {
@@ -369,7 +388,16 @@ int32_t enqueue_batch(BatchArgs a, int heuristic, const LaunchCfg& c, int32_t* q
     if (e != hipSuccess) goto fail;
     a.queue = queue;
   }
-  if (heuristic <= VSBPP_WF && c.seg != 64) {
+  if (heuristic <= VSBPP_WF && c.wpi != 1) {
+    // several wavefronts per instance
+    if (!mw_eligible(a, heuristic)) return VSBPP_E_OPTION;
+    a.spill = nullptr;
+    a.slots = round_up(a.max_items, 256);
+    int grid = 0;
+    if (c.mode == 1)
+      grid = d.cus * plain_mw_blocks_per_cu(heuristic, c.wpi, plain_mw_lds(a.slots, a.max_items));
+    e = launch_plain_mw(a, heuristic, c.wpi, grid, s);
+  } else if (heuristic <= VSBPP_WF && c.seg != 64) {
     // several instances per wavefront
     if (!seg_eligible(a, heuristic)) return VSBPP_E_OPTION;
     const SegShape sh = seg_shape(a, c.seg);

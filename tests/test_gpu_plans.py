@@ -49,6 +49,7 @@ def _launches(h):
                 out += [dict(mode=mode, lpt=lpt, waves_per_block=w) for w in (1, 2, 4, 8)]
                 out += [dict(mode=mode, lpt=lpt, waves_per_block=w, lanes_per_instance=s)
                         for s in (16, 32) for w in (1, 4)]
+                out += [dict(mode=mode, lpt=lpt, waves_per_instance=w) for w in (2, 4)]
             elif h == "H1":
                 out += [dict(mode=mode, lpt=lpt, block_threads=b) for b in (64, 256, 1024)]
             else:
