@@ -105,7 +105,8 @@ def main(argv=None):
     t5 = time.time()
     summary = {
         "criterion": args.criterion,
-        "base": args.base, "min_gain": args.min_gain,
+        "base": args.base, "min_gain": args.min_gain, "epochs": args.epochs,
+        "per_instance": args.per_instance, "lr": args.lr,
         "train_instances": args.instances, "train_m": args.m,
         "decisions": int(len(src)), "rollouts": int(n_out * n_out * len(src)),
         "label_histogram": dist.tolist(), "labels_equal_plain_choice": agree,
