@@ -4,6 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// The LLVM intrinsic behind v_writelane_b32 (this compiler has no builtin
+// for it): returns v with lane l replaced by x, both wave-uniform.
+extern "C" __device__ int vsbpp_amdgcn_writelane(int x, int l, int v) __asm(
+    "llvm.amdgcn.writelane.i32");
+
 namespace vsbpp {
 
 constexpr int kWave = 64;
@@ -29,6 +34,10 @@ __device__ __forceinline__ int32_t readlane(int32_t v, int l) {
 __device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
   uint32_t lo = readlane((uint32_t)v, l), hi = readlane((uint32_t)(v >> 32), l);
   return ((uint64_t)hi << 32) | lo;
+}
+// v with lane l (wave-uniform) set to x (wave-uniform), by v_writelane_b32
+__device__ __forceinline__ int32_t writelane(int32_t v, int32_t x, int l) {
+  return vsbpp_amdgcn_writelane(x, l, v);
 }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);

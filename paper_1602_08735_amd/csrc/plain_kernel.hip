@@ -334,10 +334,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     using Cost = typename std::conditional<sizeof(K) == 4, int32_t, int64_t>::type;
     Cost cost = 0;
     int32_t typebuf = 0;
-    // First Fit: upper bound on the room of every bin in the scan array; an
-    // item heavier than it fits nowhere, so its scan is skipped (rooms only
-    // shrink, a new bin raises the bound, and a scan that finds no fit sets it
-    // to the largest room exactly)
+    // Upper bound on the room of every bin in the scan array: an item heavier
+    // than it fits nowhere, so its scan is skipped.  Rooms only shrink, a new
+    // bin raises the bound, and a scan that finds no fit sets it to the
+    // largest room exactly.
     int32_t ub = 0;  // rooms are int32 with either key width
     for (int c = 0; c < nch; ++c) {
       const int32_t T = uniform(smin[c]);
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         const K wk = (K)w << KT::SH;
         int p = -1;
         K nk = 0;
-        const int ng = (CRIT == FF && w > ub) ? 0 : uniform((nlive + 255) >> 8);
+        const int ng = w > ub ? 0 : uniform((nlive + 255) >> 8);
         if constexpr (CRIT == FF) {
           // the lowest position among the bins the item fits: a key with its
           // halves swapped is pos << SH | room, so the least of those over
@@ -407,8 +407,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             if (ng > 0) ub = (int32_t)(~wave_min(~kmax) >> KT::SH);
             }
           }
-        } else {
+        } else if (ng > 0) {
           K best = ~(K)0;
+          // Best Fit: the largest key, whose room bounds every room
+          K kmax = 0;
           int g = 0;
           for (; g + 1 < ng; g += 2) {
             K k[4], k2[4];
@@ -418,18 +420,28 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             for (int j = 0; j < 4; ++j) {
               best = min(best, CRIT == WF ? k[j] + wk : k[j] - wk);
               best = min(best, CRIT == WF ? k2[j] + wk : k2[j] - wk);
+              if constexpr (CRIT == BF) kmax = max(kmax, max(k[j], k2[j]));
             }
           }
           if (g < ng) {
             K k[4];
             load_group(keys, g, lane, k);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) best = min(best, CRIT == WF ? k[j] + wk : k[j] - wk);
+            for (int j = 0; j < 4; ++j) {
+              best = min(best, CRIT == WF ? k[j] + wk : k[j] - wk);
+              if constexpr (CRIT == BF) kmax = max(kmax, k[j]);
+            }
           }
           best = wave_min(best);
           if (best < KT::TOP) {
             p = (int)(best & KT::POS);
             nk = best;
+          } else if constexpr (CRIT == WF) {
+            // no key wrapped: best is the least key plus w, and the least
+            // key holds the largest room
+            ub = (int32_t)(KT::R - ((best - wk) >> KT::SH));
+          } else {
+            ub = (int32_t)(~wave_min(~kmax) >> KT::SH);
           }
         }
         // decision features 0..10 (wave-uniform values): the item, the items
@@ -610,7 +622,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           }
           const int32_t Bt = readlane(cap_lane, t);
           const K room = (K)(Bt - w);
-          if constexpr (CRIT == FF) ub = max(ub, (int32_t)room);
+          ub = max(ub, (int32_t)room);
           p = nlive;
           nlive = uniform(nlive + 1);
           const int id = nb;
@@ -626,7 +638,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           }
           if (dsl && lane == 0) bload[id] = w;
           const bool out_types = !EXT || !a.src;
-          typebuf = lane == (id & 63) ? t : typebuf;
+          typebuf = writelane(typebuf, t, id & 63);
           if (out_types && (id & 63) == 63) a.types[off + (id - 63) + lane] = typebuf;
           cost += Bt;
           minroom = min(minroom, (uint32_t)room);
@@ -636,7 +648,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           }
         }
         if constexpr (EXT) placed += w;
-        mypos = lane == jj ? p : mypos;
+        mypos = writelane(mypos, p, jj);
       }
       if ((!EXT || !a.src) && q < m) a.assign[off + item] = (int32_t)pid[mypos];
     }
