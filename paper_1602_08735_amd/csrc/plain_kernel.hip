@@ -367,17 +367,24 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         const K wk = (K)w << KT::SH;
         int p = -1;
         K nk = 0;
-        const int ng = w > ub ? 0 : uniform((nlive + 255) >> 8);
-        if constexpr (CRIT == FF) {
-          // the lowest position among the bins the item fits: a key with its
-          // halves swapped is pos << SH | room, so the least of those over
-          // the fitting bins names the first fit and its room
+        if (w <= ub) {
+          // some bin may hold the item: scan the live groups.  First Fit
+          // takes the lowest position among the fitting bins (a key with its
+          // halves swapped is pos << SH | room, so the least of those names
+          // the first fit and its room); Best and Worst Fit the least
+          // candidate key.  FF/BF also keep the largest key, whose room
+          // bounds every room.
+          const int ng = uniform((nlive + 255) >> 8);
+          auto cand = [&](K key) -> K {
+            if constexpr (CRIT == FF) {
+              const K sw = (key >> KT::SH) | (key << KT::SH);
+              return key >= wk ? sw : ~(K)0;
+            } else {
+              return CRIT == WF ? key + wk : key - wk;
+            }
+          };
           K best = ~(K)0;
           K kmax = 0;
-          auto cand = [&](K key) -> K {
-            const K sw = (key >> KT::SH) | (key << KT::SH);
-            return key >= wk ? sw : ~(K)0;
-          };
           int g = 0;
           for (; g + 1 < ng; g += 2) {
             K k[4], k2[4];
@@ -386,7 +393,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               best = min(best, min(cand(k[j]), cand(k2[j])));
-              kmax = max(kmax, max(k[j], k2[j]));
+              if constexpr (CRIT != WF) kmax = max(kmax, max(k[j], k2[j]));
             }
           }
           if (g < ng) {
@@ -395,51 +402,22 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               best = min(best, cand(k[j]));
-              kmax = max(kmax, k[j]);
-            }
-          }
-          if (ng > 0) {
-            best = wave_min(best);
-            if (best != ~(K)0) {
-              p = (int)(best >> KT::SH);
-              nk = (((best & KT::POS) << KT::SH) | (K)p) - wk;
-            } else {
-            if (ng > 0) ub = (int32_t)(~wave_min(~kmax) >> KT::SH);
-            }
-          }
-        } else if (ng > 0) {
-          K best = ~(K)0;
-          // Best Fit: the largest key, whose room bounds every room
-          K kmax = 0;
-          int g = 0;
-          for (; g + 1 < ng; g += 2) {
-            K k[4], k2[4];
-            load_group(keys, g, lane, k);
-            load_group(keys, g + 1, lane, k2);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              best = min(best, CRIT == WF ? k[j] + wk : k[j] - wk);
-              best = min(best, CRIT == WF ? k2[j] + wk : k2[j] - wk);
-              if constexpr (CRIT == BF) kmax = max(kmax, max(k[j], k2[j]));
-            }
-          }
-          if (g < ng) {
-            K k[4];
-            load_group(keys, g, lane, k);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              best = min(best, CRIT == WF ? k[j] + wk : k[j] - wk);
-              if constexpr (CRIT == BF) kmax = max(kmax, k[j]);
+              if constexpr (CRIT != WF) kmax = max(kmax, k[j]);
             }
           }
           best = wave_min(best);
-          if (best < KT::TOP) {
-            p = (int)(best & KT::POS);
-            nk = best;
+          if (CRIT == FF ? best != ~(K)0 : best < KT::TOP) {
+            if constexpr (CRIT == FF) {
+              p = (int)(best >> KT::SH);
+              nk = (((best & KT::POS) << KT::SH) | (K)p) - wk;
+            } else {
+              p = (int)(best & KT::POS);
+              nk = best;
+            }
           } else if constexpr (CRIT == WF) {
             // no key wrapped: best is the least key plus w, and the least
-            // key holds the largest room
-            ub = (int32_t)(KT::R - ((best - wk) >> KT::SH));
+            // key holds the largest room (no groups: no bins, no room)
+            ub = ng > 0 ? (int32_t)(KT::R - ((best - wk) >> KT::SH)) : 0;
           } else {
             ub = (int32_t)(~wave_min(~kmax) >> KT::SH);
           }
