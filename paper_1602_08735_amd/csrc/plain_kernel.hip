@@ -76,21 +76,42 @@ __device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
   }
 }
 
-// Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
-// x: wave-uniform features; hbuf: 128 floats of LDS scratch of this wavefront.
-__device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], float* hbuf,
-                                  int lane) {
-  float acc = md->b1[lane];
+// The lane's own row of W1 and its biases, held in registers for the whole
+// kernel (lane l: hidden unit l of both layers, output l for l < 16).
+struct MlpRegs {
+  float w1[16];
+  float b1, b2, b3;
+};
+
+__device__ void load_mlp_regs(const ModelLds* md, int lane, MlpRegs& r) {
 #pragma unroll
   for (int ib = 0; ib < 4; ++ib) {
     const float4 wv = *reinterpret_cast<const float4*>(&md->w1[(ib * 64 + lane) * 4]);
-    acc = __builtin_fmaf(wv.x, x[ib * 4], acc);
-    acc = __builtin_fmaf(wv.y, x[ib * 4 + 1], acc);
-    acc = __builtin_fmaf(wv.z, x[ib * 4 + 2], acc);
-    acc = __builtin_fmaf(wv.w, x[ib * 4 + 3], acc);
+    r.w1[ib * 4] = wv.x;
+    r.w1[ib * 4 + 1] = wv.y;
+    r.w1[ib * 4 + 2] = wv.z;
+    r.w1[ib * 4 + 3] = wv.w;
+  }
+  r.b1 = md->b1[lane];
+  r.b2 = md->b2[lane];
+  r.b3 = md->b3[lane & 15];
+}
+
+// Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
+// hbuf: 128 floats of LDS scratch of this wavefront; the 16 features sit at
+// hbuf[64..79] and are read as broadcasts.
+__device__ float mlp_forward_wave(const ModelLds* md, const MlpRegs& r, float* hbuf, int lane) {
+  float acc = r.b1;
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib) {
+    const float4 xv = *reinterpret_cast<const float4*>(&hbuf[64 + ib * 4]);
+    acc = __builtin_fmaf(r.w1[ib * 4], xv.x, acc);
+    acc = __builtin_fmaf(r.w1[ib * 4 + 1], xv.y, acc);
+    acc = __builtin_fmaf(r.w1[ib * 4 + 2], xv.z, acc);
+    acc = __builtin_fmaf(r.w1[ib * 4 + 3], xv.w, acc);
   }
   hbuf[lane] = acc > 0.0f ? acc : 0.0f;
-  acc = md->b2[lane];
+  acc = r.b2;
   // weights (this lane's row) and activations (broadcasts), four 16-byte
   // words of each per LDS round trip
 #pragma unroll
@@ -116,7 +137,7 @@ __device__ float mlp_forward_wave(const ModelLds* md, const float (&x)[16], floa
   float z = 0.0f;
   if (lane < 16) {
     const int k = lane;
-    float o = md->b3[k];
+    float o = r.b3;
 #pragma unroll
     for (int jo = 0; jo < 16; jo += 4) {
       float4 wv[4], hv[4];
@@ -206,10 +227,12 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
   };
   const bool dsl = DSL && plain_ds_loads(a);
   if constexpr (!SPILL) carve(smem + model_bytes + (size_t)wave * (size_t)per_wave);
+  MlpRegs mregs;
   if constexpr (EXT) {
     if (plain_scored(a)) {
       stage_model(a.model, md);
       __syncthreads();
+      load_mlp_regs(md, lane, mregs);
     }
   }
 
@@ -294,10 +317,19 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     typename std::conditional<sizeof(K) == 4, int32_t, int64_t>::type placed = 0;
     // lanes 0..4 and 8..12 hold the bucket thresholds 1..5, the others never pass
     int32_t thr_lane = 0x7FFFFFFF;
-    float xcap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float inv_cap_lane = 0.0f;
     // 1/B_1 and 1/m of the decision features, once per instance
     float inv_b1 = 0.0f, inv_m = 0.0f;
+    // Decision features are computed one per lane (feature i in lane i):
+    // each is a product F * G of fp32 values, F a converted integer (lane 2:
+    // a quotient) and G a reciprocal (lanes 5..10: 1/max(bins, 1)).  The
+    // parts that are constants of the instance: fa_base (F's integer: B_2..B_5
+    // in lanes 11..14 for type decisions), fg_base (G: 1/B_1 or 1/m), and
+    // the histogram slot each lane reads (lanes 5..10 buckets 0..5, the
+    // others a slot that stays 0).
+    int32_t fa_base = 0;
+    float fg_base = 0.0f;
+    int32_t hslot = 7;
     if constexpr (EXT) {
       if (a.force) {
         fd = uniform(a.force[3 * (int64_t)inst]);
@@ -313,10 +345,12 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       // lane k's 1/B_k for the fill of the smallest fitting type
       inv_b1 = uniform_f(1.0f / (float)B1);
       inv_m = uniform_f(1.0f / (float)m);
-#pragma unroll
-      for (int k = 1; k <= 4; ++k)
-        xcap[k - 1] = k < n ? (float)readlane(cap_lane, k) * inv_b1 : 0.0f;
       inv_cap_lane = lane < n ? 1.0f / (float)cap_lane : 0.0f;
+      // lane l in 11..14 reads B_{l-10} from lane l - 10 (0 beyond n)
+      const int32_t cap_up = __shfl(cap_lane, lane >= 11 && lane <= 14 ? lane - 10 : 0, kWave);
+      if (a.choice_rule == 0 && lane >= 11 && lane <= 14) fa_base = cap_up;
+      fg_base = (lane == 1 || lane == 4) ? inv_m : inv_b1;
+      if (lane >= 5 && lane <= 10) hslot = lane - 5;
     }
     // rooms and capacities are int32.  The buckets of r0 (lanes 0..4) and r1
     // (lanes 8..12) in one ballot: bits 0..4 and 8..12 of it.
@@ -422,31 +456,40 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             ub = (int32_t)(~wave_min(~kmax) >> KT::SH);
           }
         }
-        // decision features 0..10 (wave-uniform values): the item, the items
-        // after it, the bins so far and their room histogram
-        auto state_features = [&](float (&x)[16]) {
+        // Decision features, feature i in lane i (i < 16), and a copy at
+        // hbuf[64..79] for the scorer.  Features 0..10: the item, the items
+        // after it, the bins so far and their room histogram; `ext` puts
+        // features 11..15 in lanes 11..15 of F's integer (bin choice), and
+        // g15 is lane 15's G (type decisions: 1/B_t of the smallest type
+        // holding the item).
+        auto lane_features = [&](auto ext, float g15) -> float {
           const int qq = (c << 6) + jj;
           const int rem = m - qq - 1;
           const int64_t rsum = total - (int64_t)placed - w;
           int32_t after = jj + 1 < kWave ? readlane(sfx, jj + 1) : 0x7FFFFFFF;
           after = min(after, next_min);
-          x[0] = (float)w * inv_b1;
-          x[1] = (float)rem * inv_m;
+          int32_t fa = hist[hslot] + fa_base;
+          fa = writelane(fa, w, 0);
+          fa = writelane(fa, rem, 1);
+          fa = writelane(fa, after, 3);
+          fa = writelane(fa, nb, 4);
+          fa = ext(fa);
           // with 32-bit keys m <= 65535 and B_1 <= 32767, so the remaining
           // weight fits int32 (whose conversion rounds as int64's does)
           const float frs = sizeof(K) == 4 ? (float)(int32_t)rsum : (float)rsum;
-          x[2] = rem > 0 ? (frs / (float)rem) * inv_b1 : 0.0f;
-          x[3] = rem > 0 ? (float)after * inv_b1 : 1.0f;
-          x[4] = (float)nb * inv_m;
-          const float inv_den = 1.0f / (float)(nb > 0 ? nb : 1);
-          const int4 h03 = *reinterpret_cast<const int4*>(hist);
-          const int4 h47 = *reinterpret_cast<const int4*>(hist + 4);
-          x[5] = (float)h03.x * inv_den;
-          x[6] = (float)h03.y * inv_den;
-          x[7] = (float)h03.z * inv_den;
-          x[8] = (float)h03.w * inv_den;
-          x[9] = (float)h47.x * inv_den;
-          x[10] = (float)h47.y * inv_den;
+          // one division for all: lane 2 the mean weight after the item
+          // (rem = 0 leaves rsum = 0, a quotient 0), the others 1/max(bins, 1)
+          const float num = __int_as_float(writelane(__float_as_int(1.0f), __float_as_int(frs), 2));
+          const int32_t den = writelane(nb > 0 ? nb : 1, rem > 0 ? rem : 1, 2);
+          const float qt = num / (float)den;
+          const float f = lane == 2 ? qt : (float)fa;
+          float g = (lane >= 5 && lane <= 10) ? qt : fg_base;
+          g = __int_as_float(writelane(__float_as_int(g), __float_as_int(g15), 15));
+          float xl = f * g;
+          // no item after this one: feature 3 is 1
+          if (rem == 0) xl = __int_as_float(writelane(__float_as_int(xl), __float_as_int(1.0f), 3));
+          hbuf[64 + lane] = xl;
+          return xl;
         };
         if constexpr (EXT) {
           // Bin choice (largest type rule, downsizing): every bin has capacity
@@ -468,15 +511,17 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
                 const int32_t cb = readlane(cap_lane, (int)__popcll(hb) - 1);
                 const int32_t ca = readlane(cap_lane, (int)__popcll(ha) - 1);
                 const int32_t cw = readlane(cap_lane, (int)__popcll(ballot(cap_lane >= w)) - 1);
-                float x[16];
-                state_features(x);
-                x[11] = (float)ra * inv_b1;
-                x[12] = (float)(ca - cb) * inv_b1;
-                x[13] = (float)cw * inv_b1;
-                x[14] = (float)(ca - L - w) * inv_b1;
-                x[15] = (float)(cb - L) * inv_b1;
+                const float xl = lane_features(
+                    [&](int32_t fa) {
+                      fa = writelane(fa, ra, 11);
+                      fa = writelane(fa, ca - cb, 12);
+                      fa = writelane(fa, cw, 13);
+                      fa = writelane(fa, ca - L - w, 14);
+                      return writelane(fa, cb - L, 15);
+                    },
+                    inv_b1);
                 if (a.choice_rule == 2) {
-                  const float z = mlp_forward_wave(md, x, hbuf, lane);
+                  const float z = mlp_forward_wave(md, mregs, hbuf, lane);
                   const float z0 = __uint_as_float(readlane(__float_as_uint(z), 0));
                   const float z1 = __uint_as_float(readlane(__float_as_uint(z), 1));
                   // a new bin only on a strictly larger score; non-finite
@@ -484,12 +529,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
                   open = __builtin_isfinite(z0) && __builtin_isfinite(z1) && z1 > z0;
                 }
                 if (dump) {
-                  if (a.feat_out && lane < 16) {
-                    float xv = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) xv = lane == k ? x[k] : xv;
-                    a.feat_out[16 * (int64_t)inst + lane] = xv;
-                  }
+                  if (a.feat_out && lane < 16) a.feat_out[16 * (int64_t)inst + lane] = xl;
                   if (a.info_out && lane == 0) {
                     a.info_out[2 * (int64_t)inst] = 3;      // keep and open both allowed
                     a.info_out[2 * (int64_t)inst + 1] = 0;  // the plain choice keeps
@@ -562,14 +602,13 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             const bool dump = d == fd && (a.feat_out || a.info_out);
             // features only where the scorer has a choice (or a dump asks)
             if ((a.type_rule == 2 && smallest > 0) || dump) {
-              float x[16];
-              state_features(x);
-#pragma unroll
-              for (int k = 0; k < 4; ++k) x[11 + k] = xcap[k];
-              x[15] = (float)w * __uint_as_float(readlane(__float_as_uint(inv_cap_lane), smallest));
+              // lanes 11..14: B_2..B_5 over B_1, lane 15: w over B_t
+              const float xl = lane_features(
+                  [&](int32_t fa) { return writelane(fa, w, 15); },
+                  __uint_as_float(readlane(__float_as_uint(inv_cap_lane), smallest)));
               // with one type holding the item the scorer has nothing to choose
               if (a.type_rule == 2 && smallest > 0) {
-                const float z = mlp_forward_wave(md, x, hbuf, lane);
+                const float z = mlp_forward_wave(md, mregs, hbuf, lane);
                 const int kmax = min(n, md->n_out);
                 // lanes 0..kmax-1 hold the scores; the choice is the lowest
                 // feasible type whose score equals the largest feasible score
@@ -581,12 +620,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
                 t = ballot(in && !__builtin_isfinite(z)) == 0ull ? bi : smallest;
               }
               if (dump) {
-                if (a.feat_out && lane < 16) {
-                  float xv = 0.0f;
-#pragma unroll
-                  for (int k = 0; k < 16; ++k) xv = lane == k ? x[k] : xv;
-                  a.feat_out[16 * (int64_t)inst + lane] = xv;
-                }
+                if (a.feat_out && lane < 16) a.feat_out[16 * (int64_t)inst + lane] = xl;
                 if (a.info_out && lane == 0) {
                   a.info_out[2 * (int64_t)inst] = (int32_t)fm;
                   a.info_out[2 * (int64_t)inst + 1] = smallest;
