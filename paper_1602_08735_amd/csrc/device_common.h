@@ -97,6 +97,16 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
   return (int32_t)(wave_min((uint32_t)v ^ 0x80000000u) ^ 0x80000000u);
 }
 
+// Inclusive prefix sum within each row of 16 lanes (all lanes active): four
+// DPP row shifts that bring in 0 past the row's start.
+__device__ __forceinline__ int32_t row_incl_sum(int32_t v) {
+  v += (int32_t)dpp<0x111>(0u, (uint32_t)v);  // row_shr:1
+  v += (int32_t)dpp<0x112>(0u, (uint32_t)v);  // row_shr:2
+  v += (int32_t)dpp<0x114>(0u, (uint32_t)v);  // row_shr:4
+  v += (int32_t)dpp<0x118>(0u, (uint32_t)v);  // row_shr:8
+  return v;
+}
+
 // Inclusive prefix sum over the 64 lanes (all lanes active).
 __device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
   const int lane = lane_id();
