@@ -81,6 +81,7 @@ __device__ void stage_model(const vsbpp_model* m, ModelLds* s) {
 struct MlpRegs {
   float w1[16];
   float b1, b2, b3;
+  int n_out;  // wave-uniform
 };
 
 __device__ void load_mlp_regs(const ModelLds* md, int lane, MlpRegs& r) {
@@ -95,6 +96,7 @@ __device__ void load_mlp_regs(const ModelLds* md, int lane, MlpRegs& r) {
   r.b1 = md->b1[lane];
   r.b2 = md->b2[lane];
   r.b3 = md->b3[lane & 15];
+  r.n_out = uniform(md->n_out);
 }
 
 // Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
@@ -135,7 +137,7 @@ __device__ float mlp_forward_wave(const ModelLds* md, const MlpRegs& r, float* h
   // inputs) and the activations as broadcasts, four 16-byte words of each
   // per LDS round trip
   float z = 0.0f;
-  if (lane < 16) {
+  if (lane < r.n_out) {
     const int k = lane;
     float o = r.b3;
 #pragma unroll
