@@ -611,11 +611,12 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
               // with one type holding the item the scorer has nothing to choose
               if (a.type_rule == 2 && smallest > 0) {
                 const float z = mlp_forward_wave(md, mregs, hbuf, lane);
-                const int kmax = min(n, md->n_out);
+                const int kmax = min(n, mregs.n_out);
                 // lanes 0..kmax-1 hold the scores; the choice is the lowest
-                // feasible type whose score equals the largest feasible score
+                // feasible type (one holding the item) whose score equals the
+                // largest feasible score
                 const bool in = lane < kmax;
-                const bool feas = in && ((fm >> lane) & 1ull);
+                const bool feas = in && cap_lane >= w;
                 const float mx = row0_max(feas ? z : -__builtin_inff());
                 const int bi = (int)__builtin_ctzll(ballot(feas && z == mx));
                 // the scorer only proposes: non-finite scores fall back
