@@ -97,6 +97,24 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
   return (int32_t)(wave_min((uint32_t)v ^ 0x80000000u) ^ 0x80000000u);
 }
 
+// Inclusive prefix maximum over the 64 lanes of non-negative values (all
+// lanes active): row shifts within each row of 16, then the last lane of each
+// row carried into the following rows.
+__device__ __forceinline__ int32_t wave_incl_max(int32_t v) {
+  v = max(v, (int32_t)dpp<0x111>(0u, (uint32_t)v));  // row_shr:1
+  v = max(v, (int32_t)dpp<0x112>(0u, (uint32_t)v));  // row_shr:2
+  v = max(v, (int32_t)dpp<0x114>(0u, (uint32_t)v));  // row_shr:4
+  v = max(v, (int32_t)dpp<0x118>(0u, (uint32_t)v));  // row_shr:8
+  v = max(v, (int32_t)dpp<kRowBcast15, 0xA>(0u, (uint32_t)v));
+  v = max(v, (int32_t)dpp<kRowBcast31, 0xC>(0u, (uint32_t)v));
+  return v;
+}
+
+// v of the lane below (lane 0: 0), by a wavefront shift
+__device__ __forceinline__ int32_t wave_shr1(int32_t v) {
+  return (int32_t)dpp<0x138>(0u, (uint32_t)v);  // wave_shr:1
+}
+
 // Inclusive prefix sum within each row of 16 lanes (all lanes active): four
 // DPP row shifts that bring in 0 past the row's start.
 __device__ __forceinline__ int32_t row_incl_sum(int32_t v) {

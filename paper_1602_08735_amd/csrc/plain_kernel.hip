@@ -375,6 +375,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     // bin raises the bound, and a scan that finds no fit sets it to the
     // largest room exactly.
     int32_t ub = 0;  // rooms are int32 with either key width
+    // Plain runs open the bins of a run of such items together (below):
+    // their costs and least room per lane, folded in at the end.
+    const bool runs = !EXT && !(BND && a.active_limit > 0);
+    Cost costv = 0;
     for (int c = 0; c < nch; ++c) {
       const int32_t T = uniform(smin[c]);
       if (nlive > 0 && (minroom < (uint32_t)T || T > tprev)) {
@@ -398,8 +402,71 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       // its bin's position and the ids are read once at the end of the chunk
       int32_t mypos = 0;
       const int cnt = min(kWave, m - (c << 6));
+      // Runs of new bins (plain runs): the bin each item of the chunk opens
+      // if nothing fits it, its type tv, capacity btv and room rv
+      int32_t tv = 0, btv = 0, rv = 0;
+      uint32_t minroomv = 0xFFFFFFFFu;
+      if (runs) {
+        if (a.type_rule != 1)
+          for (int k = 1; k < n; ++k) tv += readlane(cap_lane, k) >= wv ? 1 : 0;
+        btv = __shfl(cap_lane, tv, kWave);
+        rv = q < m ? btv - wv : 0;
+      }
       for (int jj = 0; jj < cnt; ++jj) {
         const int32_t w = readlane(wv, jj);
+        if (runs && w > ub) {
+          // Items jj, jj+1, ... open bins without a scan for as long as each
+          // is heavier than the bound, which every bin opened before it in
+          // the run raises to at least that bin's room.  Lane l (l >= jj)
+          // compares its weight with max(ub, rooms of lanes jj..l-1); the
+          // run ends at the first lane that does not exceed it (item jj
+          // does: its weight is above ub).  The run's bins take positions
+          // nlive.. and ids nb.. in item order, as one at a time would.
+          const int32_t rin = lane >= jj ? rv : 0;
+          const int32_t rsh = wave_shr1(rin);
+          const int32_t x = lane == jj ? ub : (lane > jj ? rsh : 0);
+          const int32_t pm = wave_incl_max(x);
+          const uint64_t smask = ballot(lane >= jj && lane < cnt && wv > pm);
+          // run length: the set bits of smask from bit jj (bit jj is set:
+          // pm = ub in lane jj).  All 64 set (jj = 0, a full chunk) leaves no
+          // clear bit to find, so that case is taken apart; the run always
+          // holds item jj, so the loop advances.
+          const uint64_t rest = ~(smask >> jj);
+          int L = rest == 0 ? kWave - jj : (int)__builtin_ctzll(rest);
+          L = L < 1 ? 1 : L;
+          const bool run = lane >= jj && lane < jj + L;
+          const int pos = nlive + (lane - jj);
+          // a 256-position group that starts inside the run starts empty
+          const int g0 = (nlive + 255) >> 8;
+          if ((g0 << 8) < nlive + L) fill_group(keys, g0, lane, empty_key<CRIT, K>());
+          const K room = (K)rin;
+          if (run) {
+            const K key = CRIT == WF ? (((KT::R - room) << KT::SH) | (K)pos)
+                                     : ((room << KT::SH) | (K)pos);
+            keys[kidx(pos)] = key;
+            pid[pos] = (Pid)(nb + (lane - jj));
+          }
+          mypos = run ? pos : mypos;
+          costv += run ? (Cost)btv : (Cost)0;
+          minroomv = run ? min(minroomv, (uint32_t)rin) : minroomv;
+          // types: id nb + i goes to buffer lane (nb + i) & 63, stored
+          // whenever a buffer of 64 fills
+          const int tb = nb & 63, te = tb + L;
+          const int32_t rot = __shfl(tv, (lane - (nb - jj)) & 63, kWave);
+          if (te <= kWave) {
+            typebuf = (lane >= tb && lane < te) ? rot : typebuf;
+            if (te == kWave) a.types[off + (nb - tb) + lane] = typebuf;
+          } else {
+            typebuf = lane >= tb ? rot : typebuf;
+            a.types[off + (nb - tb) + lane] = typebuf;
+            typebuf = lane < te - kWave ? rot : typebuf;
+          }
+          ub = max(ub, readlane(max(pm, rin), jj + L - 1));
+          nlive = uniform(nlive + L);
+          nb = uniform(nb + L);
+          jj += L - 1;
+          continue;
+        }
         const K wk = (K)w << KT::SH;
         int p = -1;
         K nk = 0;
@@ -665,8 +732,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         if constexpr (EXT) placed += w;
         mypos = writelane(mypos, p, jj);
       }
+      if (runs) minroom = min(minroom, wave_min(minroomv));
       if ((!EXT || !a.src) && q < m) a.assign[off + item] = (int32_t)pid[mypos];
     }
+    if (runs) cost += (Cost)wave_sum64((int64_t)costv);
     if ((!EXT || !a.src) && (nb & 63) && lane < (nb & 63))
       a.types[off + (nb & ~63) + lane] = typebuf;
     int64_t out_cost = cost;
