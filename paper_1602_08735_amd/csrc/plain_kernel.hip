@@ -369,7 +369,6 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     // with 32-bit keys m <= 65535 and B_1 <= 32767, so the cost fits int32
     using Cost = typename std::conditional<sizeof(K) == 4, int32_t, int64_t>::type;
     Cost cost = 0;
-    int32_t typebuf = 0;
     // Upper bound on the room of every bin in the scan array: an item heavier
     // than it fits nowhere, so its scan is skipped.  Rooms only shrink, a new
     // bin raises the bound, and a scan that finds no fit sets it to the
@@ -377,7 +376,8 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     int32_t ub = 0;  // rooms are int32 with either key width
     // Plain runs open the bins of a run of such items together (below):
     // their costs and least room per lane, folded in at the end.
-    const bool runs = !EXT && !(BND && a.active_limit > 0);
+    // (not compiled into the instantiations with the bounded-bins code)
+    constexpr bool runs = !EXT && !BND;
     Cost costv = 0;
     for (int c = 0; c < nch; ++c) {
       const int32_t T = uniform(smin[c]);
@@ -449,18 +449,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           mypos = run ? pos : mypos;
           costv += run ? (Cost)btv : (Cost)0;
           minroomv = run ? min(minroomv, (uint32_t)rin) : minroomv;
-          // types: id nb + i goes to buffer lane (nb + i) & 63, stored
-          // whenever a buffer of 64 fills
-          const int tb = nb & 63, te = tb + L;
-          const int32_t rot = __shfl(tv, (lane - (nb - jj)) & 63, kWave);
-          if (te <= kWave) {
-            typebuf = (lane >= tb && lane < te) ? rot : typebuf;
-            if (te == kWave) a.types[off + (nb - tb) + lane] = typebuf;
-          } else {
-            typebuf = lane >= tb ? rot : typebuf;
-            a.types[off + (nb - tb) + lane] = typebuf;
-            typebuf = lane < te - kWave ? rot : typebuf;
-          }
+          if (run) a.types[off + nb + (lane - jj)] = tv;
           ub = max(ub, readlane(max(pm, rin), jj + L - 1));
           nlive = uniform(nlive + L);
           nb = uniform(nb + L);
@@ -720,8 +709,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           }
           if (dsl && lane == 0) bload[id] = w;
           const bool out_types = !EXT || !a.src;
-          typebuf = writelane(typebuf, t, id & 63);
-          if (out_types && (id & 63) == 63) a.types[off + (id - 63) + lane] = typebuf;
+          if (out_types && lane == 0) a.types[off + id] = t;
           cost += Bt;
           minroom = min(minroom, (uint32_t)room);
           if constexpr (EXT) {
@@ -736,8 +724,6 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       if ((!EXT || !a.src) && q < m) a.assign[off + item] = (int32_t)pid[mypos];
     }
     if (runs) cost += (Cost)wave_sum64((int64_t)costv);
-    if ((!EXT || !a.src) && (nb & 63) && lane < (nb & 63))
-      a.types[off + (nb & ~63) + lane] = typebuf;
     int64_t out_cost = cost;
     if (dsl) {
       // downsized cost: every bin at the smallest capacity holding its load
