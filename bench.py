@@ -742,8 +742,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the packing path is measured on a single "
-              "MI355X (instances shard across GPUs with no exchange; no multi-GPU run is "
-              "part of this build)", file=sys.stderr)
+              "MI355X (instances shard across GPUs with no exchange, so a multi-GPU run "
+              "would be N independent copies of this one)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
