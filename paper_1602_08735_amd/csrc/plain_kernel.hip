@@ -10,6 +10,12 @@
 // order, so that is the lowest bin index.  When nothing fits, a bin of type
 // max{k : B_k >= w} (or B_1) is appended.
 //
+// An item heavier than an upper bound on every bin's room fits nowhere and
+// skips the scan.  Plain runs (no scorer, hooks or bound on the open bins)
+// open the bins of a run of such items together: each lane of a 64-item
+// chunk knows the bin its item would open, and a prefix maximum over the
+// lanes of those bins' rooms finds where the run ends.
+//
 // Bin state lives in LDS as one key per bin whose high part encodes the room
 // left (BF/FF: room, WF: R - room) and whose low part is the bin's position
 // in the scan array, so the candidate key for item w is key -/+ (w << SH) and
@@ -29,16 +35,17 @@ namespace vsbpp {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Learned bin-type scorer, evaluated by one wavefront: lane l computes hidden
-// unit l of both hidden layers and lane k output k (each unit is its bias,
-// then an fp32 fused-multiply-add chain over its inputs in index order; the
-// hidden units then take ReLU).
+// Learned scorer (bin type or bin choice), evaluated by one wavefront: lane l
+// computes hidden unit l of both hidden layers and lane k output k (each unit
+// is its bias, then an fp32 fused-multiply-add chain over its inputs in index
+// order; the hidden units then take ReLU).
 //
 // The model is staged once per workgroup at the start of LDS as fp32, laid
-// out so that lane l reads its rows of W1 and W2 as unit-stride 16-byte words
-// at immediate offsets.  Keeping the weights out of registers holds a scorer
-// wavefront under 128 VGPRs, so four of them fit a SIMD and a batch of one
-// instance per wavefront runs in a single wave of residency.
+// out so that lane l reads its rows of W2 and W3 as unit-stride 16-byte words
+// at immediate offsets; its row of W1 and its biases stay in registers.
+// Keeping W2 and W3 out of registers holds a scorer wavefront under 128 VGPRs,
+// so four of them fit a SIMD and a batch of one instance per wavefront runs
+// in a single wave of residency.
 // ---------------------------------------------------------------------------
 struct ModelLds {
   float w1[4 * 64 * 4];    // [i/4][l][4]
