@@ -42,7 +42,10 @@ namespace {
 //
 // The model is staged once per workgroup at the start of LDS as fp32, laid
 // out so that lane l reads its rows of W2 and W3 as unit-stride 16-byte words
-// at immediate offsets; its row of W1 and its biases stay in registers.
+// at immediate offsets; its row of W1 and its biases stay in registers.  A
+// layer's inputs pass once through LDS so that every 16-lane row holds them
+// all, and reach the lanes of a row through DPP row broadcasts inside the
+// fma instructions.
 // Keeping W2 and W3 out of registers holds a scorer wavefront under 128 VGPRs,
 // so four of them fit a SIMD and a batch of one instance per wavefront runs
 // in a single wave of residency.
@@ -106,66 +109,96 @@ __device__ void load_mlp_regs(const ModelLds* md, int lane, MlpRegs& r) {
   r.n_out = uniform(md->n_out);
 }
 
+// Sixteen steps of an index-order fma chain whose multiplicands come from a
+// row: step i is acc = fma(x of lane i of the lane's own 16-lane row, w[i],
+// acc).  The row value reaches every lane through the DPP row broadcast
+// (row_newbcast) of v_fmac_f32, so the activations need no LDS broadcast
+// reads; fma is exact before its one rounding, so the operand order inside it
+// changes nothing.  The compiler neither forms this instruction from its DPP
+// builtins nor sees wait states inside an asm statement: each block starts
+// with five (a DPP read after a VALU write of its source needs two, after a
+// VALU write of EXEC five) and ends with two for whatever reads acc next.
+__device__ __forceinline__ float fma_row16(float acc, float x, const float (&w)[16]) {
+  asm volatile(
+      "s_nop 4\n\t"
+      "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1"
+      : "+v"(acc)
+      : "v"(x), "v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]), "v"(w[4]), "v"(w[5]), "v"(w[6]),
+        "v"(w[7]), "v"(w[8]), "v"(w[9]), "v"(w[10]), "v"(w[11]), "v"(w[12]), "v"(w[13]),
+        "v"(w[14]), "v"(w[15]));
+  return acc;
+}
+
+// A layer's 64 activations (one per lane) rearranged so that every 16-lane
+// row holds them all: component q of lane l's result is the activation of
+// lane 16q + (l & 15).  The wavefront writes them transposed into hbuf[0..63]
+// and each lane reads four consecutive words back.
+__device__ __forceinline__ float4 rows_of(float* hbuf, float h, int lane) {
+  hbuf[((lane & 15) << 2) + (lane >> 4)] = h;
+  return *reinterpret_cast<const float4*>(&hbuf[(lane & 15) << 2]);
+}
+
+// four 16-byte words at p, p + stride, p + 2 stride, p + 3 stride (floats)
+__device__ __forceinline__ void load16(const float* p, int stride, float (&w)[16]) {
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const float4 v = *reinterpret_cast<const float4*>(p + jb * stride);
+    w[4 * jb] = v.x;
+    w[4 * jb + 1] = v.y;
+    w[4 * jb + 2] = v.z;
+    w[4 * jb + 3] = v.w;
+  }
+}
+
 // Scores of outputs 0..n_out-1 end up in lanes 0..n_out-1 (others: junk).
 // hbuf: 128 floats of LDS scratch of this wavefront; the 16 features sit at
-// hbuf[64..79] and are read as broadcasts.
+// hbuf[64..79].
 __device__ float mlp_forward_wave(const ModelLds* md, const MlpRegs& r, float* hbuf, int lane) {
-  float acc = r.b1;
-#pragma unroll
-  for (int ib = 0; ib < 4; ++ib) {
-    const float4 xv = *reinterpret_cast<const float4*>(&hbuf[64 + ib * 4]);
-    acc = __builtin_fmaf(r.w1[ib * 4], xv.x, acc);
-    acc = __builtin_fmaf(r.w1[ib * 4 + 1], xv.y, acc);
-    acc = __builtin_fmaf(r.w1[ib * 4 + 2], xv.z, acc);
-    acc = __builtin_fmaf(r.w1[ib * 4 + 3], xv.w, acc);
-  }
-  hbuf[lane] = acc > 0.0f ? acc : 0.0f;
+  // features 0..15 in every row
+  const float xf = hbuf[64 + (lane & 15)];
+  // the weights of each block of sixteen inputs are read one block ahead:
+  // W2's first block during layer 1, W3's first during W2's last
+  float w[2][16];
+  load16(&md->w2[lane * 4], 64 * 4, w[0]);
+  float acc = fma_row16(r.b1, xf, r.w1);
+  const float4 h1 = rows_of(hbuf, acc > 0.0f ? acc : 0.0f, lane);
+  // this lane's row of W2, four 16-byte words per block
+  const int k = lane & 15;
   acc = r.b2;
-  // weights (this lane's row) and activations (broadcasts), four 16-byte
-  // words of each per LDS round trip
 #pragma unroll
-  for (int jo = 0; jo < 16; jo += 4) {
-    float4 wv[4], hv[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      wv[jb] = *reinterpret_cast<const float4*>(&md->w2[((jo + jb) * 64 + lane) * 4]);
-      hv[jb] = *reinterpret_cast<const float4*>(&hbuf[(jo + jb) * 4]);
-    }
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      acc = __builtin_fmaf(wv[jb].x, hv[jb].x, acc);
-      acc = __builtin_fmaf(wv[jb].y, hv[jb].y, acc);
-      acc = __builtin_fmaf(wv[jb].z, hv[jb].z, acc);
-      acc = __builtin_fmaf(wv[jb].w, hv[jb].w, acc);
-    }
+  for (int q = 0; q < 4; ++q) {
+    if (q < 3)
+      load16(&md->w2[((4 * q + 4) * 64 + lane) * 4], 64 * 4, w[(q + 1) & 1]);
+    else
+      load16(&md->w3[k * 4], 16 * 4, w[(q + 1) & 1]);
+    acc = fma_row16(acc, q == 0 ? h1.x : (q == 1 ? h1.y : (q == 2 ? h1.z : h1.w)), w[q & 1]);
   }
-  hbuf[lane] = acc > 0.0f ? acc : 0.0f;
-  // output k on lane k: weights of row k (unit stride over k for each four
-  // inputs) and the activations as broadcasts, four 16-byte words of each
-  // per LDS round trip
-  float z = 0.0f;
-  if (lane < r.n_out) {
-    const int k = lane;
-    float o = r.b3;
+  const float4 h2 = rows_of(hbuf, acc > 0.0f ? acc : 0.0f, lane);
+  // output k = lane & 15 on every row (rows 1..3 repeat row 0's work: the
+  // broadcasts need the whole row active)
+  float o = r.b3;
 #pragma unroll
-    for (int jo = 0; jo < 16; jo += 4) {
-      float4 wv[4], hv[4];
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        wv[jb] = *reinterpret_cast<const float4*>(&md->w3[((jo + jb) * 16 + k) * 4]);
-        hv[jb] = *reinterpret_cast<const float4*>(&hbuf[(jo + jb) * 4]);
-      }
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        o = __builtin_fmaf(wv[jb].x, hv[jb].x, o);
-        o = __builtin_fmaf(wv[jb].y, hv[jb].y, o);
-        o = __builtin_fmaf(wv[jb].z, hv[jb].z, o);
-        o = __builtin_fmaf(wv[jb].w, hv[jb].w, o);
-      }
-    }
-    z = o;
+  for (int q = 0; q < 4; ++q) {
+    if (q < 3) load16(&md->w3[((4 * q + 4) * 16 + k) * 4], 16 * 4, w[(q + 1) & 1]);
+    o = fma_row16(o, q == 0 ? h2.x : (q == 1 ? h2.y : (q == 2 ? h2.z : h2.w)), w[q & 1]);
   }
-  return z;
+  return o;
 }
 
 // Largest of the floats in lanes 0..15 (none NaN), as seen by lane 0: the
