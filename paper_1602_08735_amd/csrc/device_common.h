@@ -143,13 +143,17 @@ __device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
 // ---------------------------------------------------------------------------
 constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ull;
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-  uint64_t s = seed + (k + 1ull) * kGolden;
+// the published finaliser applied to a generator state
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t s) {
   s ^= s >> 30;
   s *= 0xbf58476d1ce4e5b9ull;
   s ^= s >> 27;
   s *= 0x94d049bb133111ebull;
   return s ^ (s >> 31);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  return splitmix64_mix(seed + (k + 1ull) * kGolden);
 }
 
 // generator streams (one key per purpose, derived from the instance seed)

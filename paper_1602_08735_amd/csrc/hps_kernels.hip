@@ -668,7 +668,10 @@ __global__ void __launch_bounds__(1024) k_h2(BatchArgs a, int nbslots, int group
 //
 // Rule-1 positions, their weights and the bin each item opens when nothing
 // fits are resolved a chunk of rounds at a time by the whole workgroup, and
-// every packer starts from a per-instance template of its Rule-2 bins.  A
+// every packer starts from a per-instance template of its Rule-2 bins.  The
+// first placement of a packing meets only those bins, so the chunk step also
+// records, per position and criterion, the bin it takes there: a packing's
+// first item needs no scan.  A
 // round (spr subsets) needs two barriers: one for the group minimum, one
 // before the bin counts of all groups are read.  The winner's own wave then
 // writes its assignment and bin types, one lane per item and one per bin,
@@ -698,15 +701,23 @@ k_h2s(BatchArgs a, int nbslots, int group) {
   const int spr = B / group;  // subsets per round
   int32_t* arrA = reinterpret_cast<int32_t*>(smem);
   int32_t* tmplA = arrA + (size_t)nbslots * B;  // [nbslots]
-  int32_t* s_ci = tmplA + nbslots;              // [B] chunk items
-  // [B] per chunk position: {w << 10, type of the bin the item opens when
-  // nothing fits}, one 8-byte read per placement
-  int2* s_cwt = reinterpret_cast<int2*>(s_ci + B);
-  int32_t* s_u = s_ci + 3 * B;                  // [spr] used bins
+  // [B] per chunk position: the first placement's bin for each criterion
+  // (below)
+  uint32_t* s_first = reinterpret_cast<uint32_t*>(tmplA + nbslots);
+  // [B] per chunk position: {w << 10, the type of the bin the item opens
+  // when nothing fits | item << 5}, one 8-byte read per placement
+  int2* s_cwt = reinterpret_cast<int2*>(s_first + B);
+  int32_t* s_u = tmplA + nbslots + 3 * B;       // [spr] used bins
   int32_t* s_cst = s_u + spr;                   // [spr] subset cost
   int32_t* myA = arrA + ((tid >> 6) * nbslots) * 64 + (tid & 63);
   const int g = tid / group, r = tid - g * group;
   const int lane = lane_id(), wave = tid >> 6, wpg = group >> 6;
+  // this packer's part of its generator state: output I * P + r of the H2
+  // stream has state key + (I * P + r + 1) * gamma, whose part
+  // (r + 1) * gamma is fixed for the thread (kept opaque, so that the
+  // compiler does not fold the two products back into one per round)
+  uint64_t st_lane = (uint64_t)(r + 1) * kGolden;
+  asm volatile("" : "+v"(st_lane));
   if (tid < 12) {
     const int c = tid >> 2, f = tid & 3;
     const bool wf = c == WF;
@@ -770,13 +781,26 @@ k_h2s(BatchArgs a, int nbslots, int group) {
         if (tid < chunk_rounds * per_round && q < m) {
           const int item = a.order ? a.order[off + q] : (int)perm.at((uint32_t)q);
           const int32_t w = a.w[off + item];
-          s_ci[tid] = item;
           // the bin this item opens when nothing fits: the smallest capacity
           // >= w (the capacities decrease, so the last of those), or B_1
           int t = 0;
           if (a.type_rule != 1)
             for (int kk = 1; kk < n; ++kk) t += s_caps[kk] >= w ? 1 : 0;
-          s_cwt[tid] = make_int2(w << 10, t);
+          // item < 2^16: this kernel takes instances of at most 65535 items
+          s_cwt[tid] = make_int2(w << 10, t | (item << 5));
+          // Its first placement in any permutation finds the Rule-2 bins
+          // of the template, and B_1 among them holds it (no weight exceeds
+          // B_1): per criterion c, the low ten bits (slot << 5 | type) of the
+          // least key over those bins, at bit 10c.
+          uint32_t f = 0;
+          for (int c = 0; c < 3; ++c) {
+            const uint32_t xx = ((uint32_t)(w << 10) ^ s_keyc[4 * c + 1]) + s_keyc[4 * c + 2];
+            uint32_t best = 0xFFFFFFFFu;
+            for (int b = 0; b < n; ++b)
+              best = min(best, (((uint32_t)tmplA[b] ^ s_keyc[4 * c]) + xx) & s_keyc[4 * c + 3]);
+            f |= (best & 1023u) << (10 * c);
+          }
+          s_first[tid] = f;
         }
         __syncthreads();
       }
@@ -810,61 +834,24 @@ k_h2s(BatchArgs a, int nbslots, int group) {
         // 3^6 over at most six placements).
         uint32_t cu = a.force_crit >= 0
                           ? (a.force_crit == 0 ? 0u : (a.force_crit == 1 ? 0x80000000u : 0xFFFFFFFFu))
-                          : digits_word(ck, (uint64_t)I * (uint64_t)P + (uint64_t)r);
+                          : (uint32_t)(splitmix64_mix(ck + (uint64_t)I * (uint64_t)P * kGolden +
+                                                      st_lane) >> 32);
         int nb = n;
-        // the most bins any packer of the wave holds (wave-uniform; every
-        // packer starts with the n Rule-2 bins)
-        int nbw = n;
+        // slot groups that hold a bin of some packer of the wave
+        // (wave-uniform; every packer starts with the n Rule-2 bins, and a
+        // placement adds at most two, so one ballot per placement keeps
+        // 4 ng at or above every packer's count)
+        int ng = (n + 3) >> 2;
         int sh = 0;
-        for (int t = 0; t < k; ++t) {
-          const int d = (pm >> (4 * t)) & 0xF;
-          const int2 wt = s_cwt[lq + d];
-          const uint32_t W10 = (uint32_t)wt.x;  // w << 10
-          const int32_t tn = wt.y;
-          // the criterion digit floor(3u / 2^32) times 16, the byte offset of
-          // its key constants: floor(48u / 2^32) with the low four bits cleared
-          const uint32_t koff = __umulhi(cu, 48u) & 0x30u;
-          cu *= 3u;
-          // x = XW or -W10, as (W10 ^ nm) + ad
-          const uint4 kc = *reinterpret_cast<const uint4*>(
-              reinterpret_cast<const unsigned char*>(s_keyc) + koff);
-          const uint32_t sx = kc.x;
-          const uint32_t x = (W10 ^ kc.y) + kc.z;
-          const uint32_t msk = kc.w;
-          // groups that hold a bin of some packer of the wave
-          const int ng = (min(nbslots, nbw) + 3) >> 2;
-          // two groups per LDS round trip, then an odd last group alone
-          uint32_t best = 0xFFFFFFFFu;
-          int gi = 0;
-          for (; gi + 1 < ng; gi += 2) {
-            const uint32_t* const pg = reinterpret_cast<const uint32_t*>(myA + 256 * gi);
-            const uint4 v = make_uint4(pg[0], pg[64], pg[128], pg[192]);
-            const uint4 u = make_uint4(pg[256], pg[320], pg[384], pg[448]);
-            const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
-            const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
-            const uint32_t k4 = ((u.x ^ sx) + x) & msk, k5 = ((u.y ^ sx) + x) & msk;
-            const uint32_t k6 = ((u.z ^ sx) + x) & msk, k7 = ((u.w ^ sx) + x) & msk;
-            // one three-way minimum per two keys
-            best = min(min(best, k0), k1);
-            best = min(min(best, k2), k3);
-            best = min(min(best, k4), k5);
-            best = min(min(best, k6), k7);
-          }
-          if (gi < ng) {
-            const uint32_t* const pg = reinterpret_cast<const uint32_t*>(myA + 256 * gi);
-            const uint4 v = make_uint4(pg[0], pg[64], pg[128], pg[192]);
-            const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
-            const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
-            best = min(min(best, k0), k1);
-            best = min(min(best, k2), k3);
-          }
-          // The chosen bin, or a new bin of the item's type (resolved with
-          // its chunk) at the next free slot.  Both cases run the same
-          // straight-line code: permutations of a wave take different
-          // branches, and selects cost less than both branch bodies.
-          const bool found = best < (1u << 25);
-          const int b = found ? (int)((best >> 5) & 31u) : nb;
-          const int type = found ? (int)(best & 31u) : tn;
+        // Puts the item (W10 = w << 10; tw: the type of the bin it opens
+        // when nothing fits, in the low five bits) into the bin whose key's
+        // low bits are bt when found, else into a new bin at the next free
+        // slot.  Both cases run the same straight-line code: permutations of
+        // a wave take different branches, and selects cost less than both
+        // branch bodies.
+        auto place = [&](bool found, uint32_t bt, uint32_t W10, uint32_t tw) {
+          const int b = found ? (int)((bt >> 5) & 31u) : nb;
+          const int type = (int)((found ? bt : tw) & 31u);
           int32_t* const pb = slot_at(myA, b);
           const int32_t word = *pb;  // a free slot holds an empty bin word
           const int4 ty = s_type[type];
@@ -896,9 +883,61 @@ k_h2s(BatchArgs a, int nbslots, int group) {
           // the bin of placement t, 5 bits at 5t
           locs |= (uint32_t)b << sh;
           sh += 5;
-          // a placement adds at most two bins to a packer
-          if (ballot(nb > nbw)) ++nbw;
-          if (ballot(nb > nbw)) ++nbw;
+          if (ballot(nb > 4 * ng)) ++ng;
+        };
+        {
+          // the first placement from the chunk's table: criterion digit c
+          // picks bits 10c.. of the item's entry (the template's bins only;
+          // one of them always holds the item)
+          const int d = pm & 0xF;
+          const int2 wt = s_cwt[lq + d];
+          const uint32_t f = s_first[lq + d];
+          const uint32_t c = __umulhi(cu, 3u);
+          cu *= 3u;
+          place(true, f >> (10u * c), (uint32_t)wt.x, (uint32_t)wt.y);
+        }
+        for (int t = 1; t < k; ++t) {
+          const int d = (pm >> (4 * t)) & 0xF;
+          const int2 wt = s_cwt[lq + d];
+          const uint32_t W10 = (uint32_t)wt.x;  // w << 10
+          // the criterion digit floor(3u / 2^32) times 16, the byte offset of
+          // its key constants: floor(48u / 2^32) with the low four bits cleared
+          const uint32_t koff = __umulhi(cu, 48u) & 0x30u;
+          cu *= 3u;
+          // x = XW or -W10, as (W10 ^ nm) + ad
+          const uint4 kc = *reinterpret_cast<const uint4*>(
+              reinterpret_cast<const unsigned char*>(s_keyc) + koff);
+          const uint32_t sx = kc.x;
+          const uint32_t x = (W10 ^ kc.y) + kc.z;
+          const uint32_t msk = kc.w;
+          // two groups per LDS round trip, then an odd last group alone
+          uint32_t best = 0xFFFFFFFFu;
+          int gi = 0;
+          for (; gi + 1 < ng; gi += 2) {
+            const uint32_t* const pg = reinterpret_cast<const uint32_t*>(myA + 256 * gi);
+            const uint4 v = make_uint4(pg[0], pg[64], pg[128], pg[192]);
+            const uint4 u = make_uint4(pg[256], pg[320], pg[384], pg[448]);
+            const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
+            const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
+            const uint32_t k4 = ((u.x ^ sx) + x) & msk, k5 = ((u.y ^ sx) + x) & msk;
+            const uint32_t k6 = ((u.z ^ sx) + x) & msk, k7 = ((u.w ^ sx) + x) & msk;
+            // one three-way minimum per two keys
+            best = min(min(best, k0), k1);
+            best = min(min(best, k2), k3);
+            best = min(min(best, k4), k5);
+            best = min(min(best, k6), k7);
+          }
+          if (gi < ng) {
+            const uint32_t* const pg = reinterpret_cast<const uint32_t*>(myA + 256 * gi);
+            const uint4 v = make_uint4(pg[0], pg[64], pg[128], pg[192]);
+            const uint32_t k0 = ((v.x ^ sx) + x) & msk, k1 = ((v.y ^ sx) + x) & msk;
+            const uint32_t k2 = ((v.z ^ sx) + x) & msk, k3 = ((v.w ^ sx) + x) & msk;
+            best = min(min(best, k0), k1);
+            best = min(min(best, k2), k3);
+          }
+          // the chosen bin, or a new bin of the item's type (resolved with
+          // its chunk) at the next free slot
+          place(best < (1u << 25), best, W10, (uint32_t)wt.y);
         }
         used = ~nused;
         key = ((uint32_t)cost << 10) | (uint32_t)r;
@@ -939,7 +978,8 @@ k_h2s(BatchArgs a, int nbslots, int group) {
         if (lane < k) {
           const int b = (int)((wlocs >> (5 * lane)) & 31u);
           const int d = (int)((wpm >> (4 * lane)) & 0xFu);
-          a.assign[off + s_ci[lq + d]] = before + (int)__popc(wused & ((1u << b) - 1u));
+          a.assign[off + (s_cwt[lq + d].y >> 5)] =
+              before + (int)__popc(wused & ((1u << b) - 1u));
         }
         if (lane < 32 && ((wused >> lane) & 1u)) {
           a.types[off + before + (int)__popc(wused & ((1u << lane) - 1u))] =
