@@ -115,35 +115,47 @@ __device__ void load_mlp_regs(const ModelLds* md, int lane, MlpRegs& r) {
 // (row_newbcast) of v_fmac_f32, so the activations need no LDS broadcast
 // reads; fma is exact before its one rounding, so the operand order inside it
 // changes nothing.  The compiler neither forms this instruction from its DPP
-// builtins nor sees wait states inside an asm statement: each block starts
-// with five (a DPP read after a VALU write of its source needs two, after a
-// VALU write of EXEC five) and ends with two for whatever reads acc next.
+// builtins nor sees wait states inside an asm statement, so the blocks carry
+// their own: a layer's first block starts with five (a DPP read after a VALU
+// write of EXEC needs five), the others with two (after a VALU write of the
+// DPP source, should the compiler move x between blocks), and a layer's last
+// block ends with two for whatever reads acc next.
+#define VSBPP_FMA_ROW16_BODY(PRE, POST)                                                     \
+  asm volatile(PRE                                                                          \
+               "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"    \
+               "v_fmac_f32_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"   \
+               "v_fmac_f32_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"   \
+               "v_fmac_f32_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"  \
+               "v_fmac_f32_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"  \
+               "v_fmac_f32_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"  \
+               "v_fmac_f32_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"  \
+               "v_fmac_f32_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"  \
+               "v_fmac_f32_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf" POST \
+               : "+v"(acc)                                                                  \
+               : "v"(x), "v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]), "v"(w[4]), "v"(w[5]),  \
+                 "v"(w[6]), "v"(w[7]), "v"(w[8]), "v"(w[9]), "v"(w[10]), "v"(w[11]),         \
+                 "v"(w[12]), "v"(w[13]), "v"(w[14]), "v"(w[15]))
+
+template <bool FIRST, bool LAST>
 __device__ __forceinline__ float fma_row16(float acc, float x, const float (&w)[16]) {
-  asm volatile(
-      "s_nop 4\n\t"
-      "v_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
-      "s_nop 1"
-      : "+v"(acc)
-      : "v"(x), "v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]), "v"(w[4]), "v"(w[5]), "v"(w[6]),
-        "v"(w[7]), "v"(w[8]), "v"(w[9]), "v"(w[10]), "v"(w[11]), "v"(w[12]), "v"(w[13]),
-        "v"(w[14]), "v"(w[15]));
+  if constexpr (FIRST && LAST)
+    VSBPP_FMA_ROW16_BODY("s_nop 4\n\t", "\n\ts_nop 1");
+  else if constexpr (FIRST)
+    VSBPP_FMA_ROW16_BODY("s_nop 4\n\t", "");
+  else if constexpr (LAST)
+    VSBPP_FMA_ROW16_BODY("s_nop 1\n\t", "\n\ts_nop 1");
+  else
+    VSBPP_FMA_ROW16_BODY("s_nop 1\n\t", "");
   return acc;
 }
+#undef VSBPP_FMA_ROW16_BODY
 
 // A layer's 64 activations (one per lane) rearranged so that every 16-lane
 // row holds them all: component q of lane l's result is the activation of
@@ -176,7 +188,7 @@ __device__ float mlp_forward_wave(const ModelLds* md, const MlpRegs& r, float* h
   // W2's first block during layer 1, W3's first during W2's last
   float w[2][16];
   load16(&md->w2[lane * 4], 64 * 4, w[0]);
-  float acc = fma_row16(r.b1, xf, r.w1);
+  float acc = fma_row16<true, true>(r.b1, xf, r.w1);
   const float4 h1 = rows_of(hbuf, acc > 0.0f ? acc : 0.0f, lane);
   // this lane's row of W2, four 16-byte words per block
   const int k = lane & 15;
@@ -187,7 +199,13 @@ __device__ float mlp_forward_wave(const ModelLds* md, const MlpRegs& r, float* h
       load16(&md->w2[((4 * q + 4) * 64 + lane) * 4], 64 * 4, w[(q + 1) & 1]);
     else
       load16(&md->w3[k * 4], 16 * 4, w[(q + 1) & 1]);
-    acc = fma_row16(acc, q == 0 ? h1.x : (q == 1 ? h1.y : (q == 2 ? h1.z : h1.w)), w[q & 1]);
+    const float xq = q == 0 ? h1.x : (q == 1 ? h1.y : (q == 2 ? h1.z : h1.w));
+    if (q == 0)
+      acc = fma_row16<true, false>(acc, xq, w[0]);
+    else if (q == 3)
+      acc = fma_row16<false, true>(acc, xq, w[1]);
+    else
+      acc = fma_row16<false, false>(acc, xq, w[q & 1]);
   }
   const float4 h2 = rows_of(hbuf, acc > 0.0f ? acc : 0.0f, lane);
   // output k = lane & 15 on every row (rows 1..3 repeat row 0's work: the
@@ -196,7 +214,13 @@ __device__ float mlp_forward_wave(const ModelLds* md, const MlpRegs& r, float* h
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (q < 3) load16(&md->w3[((4 * q + 4) * 16 + k) * 4], 16 * 4, w[(q + 1) & 1]);
-    o = fma_row16(o, q == 0 ? h2.x : (q == 1 ? h2.y : (q == 2 ? h2.z : h2.w)), w[q & 1]);
+    const float xq = q == 0 ? h2.x : (q == 1 ? h2.y : (q == 2 ? h2.z : h2.w));
+    if (q == 0)
+      o = fma_row16<true, false>(o, xq, w[0]);
+    else if (q == 3)
+      o = fma_row16<false, true>(o, xq, w[1]);
+    else
+      o = fma_row16<false, false>(o, xq, w[q & 1]);
   }
   return o;
 }
