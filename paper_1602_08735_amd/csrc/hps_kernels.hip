@@ -960,14 +960,14 @@ k_h2s(BatchArgs a, int nbslots, int group) {
       // canonical ids: this subset's bins follow those of earlier subsets.
       // Lane i < spr (<= 16) holds subset i's bin count and cost; prefix
       // sums over the first row give every wave the counts before its
-      // subset and the round's totals (a round's cost fits int32: at most
-      // 16 subsets of a few bins of capacity <= 32767).
+      // subset and the round's total, and the first wave (which writes the
+      // instance's cost) the round's cost (a round's cost fits int32: at
+      // most 16 subsets of a few bins of capacity <= 32767).
       const int32_t pu = row_incl_sum(lane < spr ? s_u[lane] : 0);
-      const int32_t pc = row_incl_sum(lane < spr ? s_cst[lane] : 0);
       const int gw = uniform(g);  // a group is a whole number of wavefronts
       const int32_t before = carry + (gw > 0 ? readlane(pu, gw - 1) : 0);
       carry += readlane(pu, spr - 1);
-      cost_acc += readlane(pc, spr - 1);
+      if (wave == 0) cost_acc += readlane(row_incl_sum(lane < spr ? s_cst[lane] : 0), spr - 1);
       // the winner's wave writes its result: lane t the item of placement
       // t, lane b the type of bin slot b if used
       const int wr = (int)(gm & 1023u);  // the winning rank
