@@ -81,9 +81,10 @@ enum {
   VSBPP_E_OPTION = -6,    /* bad option (s1, s2, type rule, criterion, order) */
   VSBPP_E_DEVICE = -7,    /* no usable gfx950 device or a HIP runtime error   */
   VSBPP_E_NOMEM = -8,     /* device allocation failed                          */
-  VSBPP_E_MODEL = -9      /* the learned type rule without a model, or a model
+  VSBPP_E_MODEL = -9      /* the learned type rule without a model, a model
                              file that is missing, of the wrong size, with
-                             n_out outside 1..16 or a non-finite parameter    */
+                             n_out outside 1..16 or a non-finite parameter,
+                             or a buffer that is not a trainer checkpoint     */
 };
 /* Argument checks run in this order and the first failure is returned:
  * NULL, SIZE, CAPS, WEIGHT, HEURISTIC, OPTION, MODEL. */
@@ -513,6 +514,19 @@ int32_t vsbpp_trainer_gradient(vsbpp_trainer* tr, const float* d_x, const int32_
 const vsbpp_model* vsbpp_trainer_device_model(const vsbpp_trainer* tr);
 /* Copies the current bf16 model to host memory (synchronous). */
 int32_t vsbpp_trainer_export(const vsbpp_trainer* tr, vsbpp_model* out);
+/* Checkpoint and resume (for callers that train in several sessions): the
+ * trainer's whole state -- its step count (Adam's bias correction), current
+ * bf16 model, fp32 master weights and both Adam moments -- as one host byte
+ * buffer of vsbpp_trainer_state_bytes(tr) bytes (negative: VSBPP_E_NULL).
+ * vsbpp_trainer_save writes it into buf (cap bytes; VSBPP_E_SIZE when
+ * smaller); vsbpp_trainer_restore loads one into a trainer created with the
+ * same n_out (VSBPP_E_SIZE on a size or n_out mismatch, VSBPP_E_MODEL when
+ * buf is not a trainer checkpoint), after which steps continue exactly as
+ * they would have in the saved trainer.  Both synchronise the device; the
+ * caller owns buf. */
+int64_t vsbpp_trainer_state_bytes(const vsbpp_trainer* tr);
+int32_t vsbpp_trainer_save(const vsbpp_trainer* tr, void* buf, int64_t cap);
+int32_t vsbpp_trainer_restore(vsbpp_trainer* tr, const void* buf, int64_t size);
 void vsbpp_trainer_destroy(vsbpp_trainer* tr);
 
 /* Lower bounds of the optimum of every instance of a device CSR batch (the

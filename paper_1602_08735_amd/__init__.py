@@ -34,7 +34,8 @@ EXPORTS = (
     "vsbpp_plan_run", "vsbpp_plan_launch", "vsbpp_plan_destroy", "vsbpp_last_error",
     "vsbpp_pack_batch_ex", "vsbpp_rollout_labels", "vsbpp_trainer_create",
     "vsbpp_trainer_step", "vsbpp_trainer_gradient", "vsbpp_trainer_device_model",
-    "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_lower_bounds",
+    "vsbpp_trainer_export", "vsbpp_trainer_destroy", "vsbpp_trainer_state_bytes",
+    "vsbpp_trainer_save", "vsbpp_trainer_restore", "vsbpp_lower_bounds",
     "vsbpp_plan_create_ex", "vsbpp_exact_batch", "vsbpp_cost", "vsbpp_lower_bound",
     "vsbpp_model_load", "vsbpp_model_free", "vsbpp_measure_peaks",
     "vsbpp_pack_batch_static",
@@ -498,6 +499,12 @@ def _learn_lib():
         L.vsbpp_trainer_export.argtypes = [vp, ctypes.POINTER(Model)]
         L.vsbpp_trainer_destroy.restype = None
         L.vsbpp_trainer_destroy.argtypes = [vp]
+        L.vsbpp_trainer_state_bytes.restype = ctypes.c_int64
+        L.vsbpp_trainer_state_bytes.argtypes = [vp]
+        L.vsbpp_trainer_save.restype = i32
+        L.vsbpp_trainer_save.argtypes = [vp, vp, ctypes.c_int64]
+        L.vsbpp_trainer_restore.restype = i32
+        L.vsbpp_trainer_restore.argtypes = [vp, vp, ctypes.c_int64]
         L.vsbpp_plan_create_ex.restype = i32
         L.vsbpp_plan_create_ex.argtypes = [ctypes.POINTER(_BatchDesc), i32, ctypes.POINTER(Options),
                                            vp, ctypes.POINTER(Launch), ctypes.c_uint32,
@@ -628,6 +635,26 @@ class Trainer:
         if rc != 0:
             raise VsbppError(rc, "vsbpp_trainer_export")
         return m
+
+    def state(self) -> bytes:
+        """The trainer's whole state (step, model, master weights, Adam
+        moments) as bytes (vsbpp_trainer_save)."""
+        L = _learn_lib()
+        n = L.vsbpp_trainer_state_bytes(self._h)
+        if n < 0:
+            raise VsbppError(int(n), "vsbpp_trainer_state_bytes")
+        buf = ctypes.create_string_buffer(int(n))
+        rc = L.vsbpp_trainer_save(self._h, buf, n)
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_trainer_save")
+        return buf.raw
+
+    def restore(self, state: bytes) -> None:
+        """Loads a state written by state() (vsbpp_trainer_restore)."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        rc = _learn_lib().vsbpp_trainer_restore(self._h, buf, len(state))
+        if rc != 0:
+            raise VsbppError(rc, "vsbpp_trainer_restore")
 
     def close(self):
         if getattr(self, "_h", None):

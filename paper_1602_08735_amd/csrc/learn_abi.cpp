@@ -54,6 +54,18 @@ int32_t fail() {
   return VSBPP_E_DEVICE;
 }
 
+// A trainer checkpoint: this header, the current bf16 model (vsbpp_model as
+// laid out in memory), then the fp32 master weights and Adam's first and
+// second moments, np floats each.
+constexpr char kTrainerMagic[8] = {'V', 'S', 'B', 'P', 'T', 'R', 'N', '1'};
+struct TrainerStateHeader {
+  char magic[8];
+  int32_t n_out;
+  int32_t np;
+  int32_t step;
+  int32_t reserved;
+};
+
 }  // namespace
 
 extern "C" {
@@ -248,6 +260,61 @@ int32_t vsbpp_trainer_export(const vsbpp_trainer* t, vsbpp_model* out) {
   if (hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(out, t->d_model, sizeof(vsbpp_model), hipMemcpyDeviceToHost) != hipSuccess)
     return fail();
+  return VSBPP_OK;
+}
+
+int64_t vsbpp_trainer_state_bytes(const vsbpp_trainer* t) {
+  if (!t) return VSBPP_E_NULL;
+  return (int64_t)(sizeof(TrainerStateHeader) + sizeof(vsbpp_model) +
+                   3 * sizeof(float) * (size_t)t->np);
+}
+
+int32_t vsbpp_trainer_save(const vsbpp_trainer* t, void* buf, int64_t cap) {
+  if (!t || !buf) return VSBPP_E_NULL;
+  const int64_t need = vsbpp_trainer_state_bytes(t);
+  if (cap < need) return VSBPP_E_SIZE;
+  unsigned char* p = static_cast<unsigned char*>(buf);
+  TrainerStateHeader h{};
+  std::memcpy(h.magic, kTrainerMagic, sizeof h.magic);
+  h.n_out = t->nout;
+  h.np = t->np;
+  h.step = t->step;
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  const size_t pb = sizeof(float) * (size_t)t->np;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(p, t->d_model, sizeof(vsbpp_model), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(p + sizeof(vsbpp_model), t->master, pb, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(p + sizeof(vsbpp_model) + pb, t->m1, pb, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(p + sizeof(vsbpp_model) + 2 * pb, t->m2, pb, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return fail();
+  return VSBPP_OK;
+}
+
+int32_t vsbpp_trainer_restore(vsbpp_trainer* t, const void* buf, int64_t size) {
+  if (!t || !buf) return VSBPP_E_NULL;
+  if (size < (int64_t)sizeof(TrainerStateHeader)) return VSBPP_E_SIZE;
+  const unsigned char* p = static_cast<const unsigned char*>(buf);
+  TrainerStateHeader h;
+  std::memcpy(&h, p, sizeof h);
+  if (std::memcmp(h.magic, kTrainerMagic, sizeof h.magic) != 0) return VSBPP_E_MODEL;
+  if (h.n_out != t->nout || h.np != t->np || h.step < 0) return VSBPP_E_SIZE;
+  if (size != vsbpp_trainer_state_bytes(t)) return VSBPP_E_SIZE;
+  p += sizeof h;
+  vsbpp_model m;
+  std::memcpy(&m, p, sizeof m);
+  if (m.n_out != t->nout) return VSBPP_E_MODEL;
+  const size_t pb = sizeof(float) * (size_t)t->np;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(t->d_model, p, sizeof(vsbpp_model), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->master, p + sizeof(vsbpp_model), pb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->m1, p + sizeof(vsbpp_model) + pb, pb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->m2, p + sizeof(vsbpp_model) + 2 * pb, pb, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return fail();
+  t->step = h.step;
   return VSBPP_OK;
 }
 

@@ -165,15 +165,36 @@ def lookahead_labels(db: DeviceBatch, crit, src, d, info, n_types: int,
 
 def train(x, mask, label, n_out: int, *, epochs: int = 4, batch: int = 4096,
           lr: float = 2e-3, rng: np.random.Generator, init: Model | None = None,
-          log=None):
+          log=None, checkpoint: str | None = None, resume: bool = False):
     """Adam on the masked softmax cross-entropy; minibatches are a fresh
-    permutation of the samples every epoch."""
+    permutation of the samples every epoch.
+
+    With ``checkpoint``, the state after every epoch goes to that file (the
+    trainer's state from vsbpp_trainer_save) and ``checkpoint + ".json"``
+    (the epochs done, the losses so far and the state of ``rng``); with
+    ``resume`` as well, training continues from them when they exist, and
+    ends with the same weights as an uninterrupted run on the same data."""
+    import json
+    import os
+
     import torch
 
     tr = Trainer(init if init is not None else init_model(n_out, rng))
     n = int(x.shape[0])
     losses = []
-    for ep in range(epochs):
+    start = 0
+    meta_path = checkpoint + ".json" if checkpoint else None
+    if checkpoint and resume and os.path.exists(checkpoint) and os.path.exists(meta_path):
+        with open(meta_path) as f:
+            meta = json.load(f)
+        with open(checkpoint, "rb") as f:
+            tr.restore(f.read())
+        start = int(meta["epochs_done"])
+        losses = [float(v) for v in meta["losses"]]
+        rng.bit_generator.state = meta["rng_state"]
+        if log:
+            log(f"resumed after epoch {start - 1}")
+    for ep in range(start, epochs):
         perm = torch.as_tensor(rng.permutation(n).astype(np.int32), device="cuda")
         for s in range(0, n - batch + 1, batch):
             want = s == 0
@@ -182,6 +203,17 @@ def train(x, mask, label, n_out: int, *, epochs: int = 4, batch: int = 4096,
                 losses.append(loss)
                 if log:
                     log(f"epoch {ep} loss {loss:.4f}")
+        if checkpoint:
+            # the state file first, then its description: a description on
+            # disk always names a complete state
+            tmp = checkpoint + ".tmp"
+            with open(tmp, "wb") as f:
+                f.write(tr.state())
+            os.replace(tmp, checkpoint)
+            with open(meta_path + ".tmp", "w") as f:
+                json.dump({"epochs_done": ep + 1, "losses": losses,
+                           "rng_state": rng.bit_generator.state}, f)
+            os.replace(meta_path + ".tmp", meta_path)
     torch.cuda.synchronize()
     return tr, losses
 

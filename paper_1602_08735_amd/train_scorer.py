@@ -50,6 +50,10 @@ def main(argv=None):
                     help="keep a label other than the base rule's choice only when its "
                          "lookahead value beats the base choice's by at least this much")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--checkpoint", default=None,
+                    help="write the trainer's state here after every epoch")
+    ap.add_argument("--resume", action="store_true",
+                    help="continue from --checkpoint when it exists")
     args = ap.parse_args(argv)
 
     import torch
@@ -93,7 +97,8 @@ def main(argv=None):
         f"label histogram {dist.tolist()}, equal to the plain choice {agree:.3f}")
     mask = info[:, 0].contiguous()
     tr, losses = learned.train(x, mask, labels, n_out, epochs=args.epochs, batch=args.batch,
-                               lr=args.lr, rng=rng, log=log)
+                               lr=args.lr, rng=rng, log=log, checkpoint=args.checkpoint,
+                               resume=args.resume)
     t4 = time.time()
     model = tr.export()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

@@ -272,6 +272,18 @@ def test_model_load_checks(V, tmp_path):
     L.vsbpp_model_free(None)
 
 
+def test_trainer_checkpoint_null_checks(V):
+    L = ctypes.CDLL(V.LIB_PATH)
+    L.vsbpp_trainer_state_bytes.restype = ctypes.c_int64
+    L.vsbpp_trainer_state_bytes.argtypes = [ctypes.c_void_p]
+    L.vsbpp_trainer_save.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    L.vsbpp_trainer_restore.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    buf = ctypes.create_string_buffer(64)
+    assert L.vsbpp_trainer_state_bytes(None) == -1
+    assert L.vsbpp_trainer_save(None, buf, 64) == -1
+    assert L.vsbpp_trainer_restore(None, buf, 64) == -1
+
+
 def test_learned_rule_without_model(V):
     L = V._learn_lib()
     d = V._BatchDesc()

@@ -220,6 +220,50 @@ def test_training_gradient_matches_float64(V, L):
     assert bytes(t1.export()) == bytes(t2.export())
 
 
+def test_training_checkpoint_resume(V, L, tmp_path):
+    """Training stopped after two epochs and resumed from its checkpoint (a
+    new trainer, a new generator) ends with the weights and losses of four
+    uninterrupted epochs; a foreign buffer or another output count is
+    refused."""
+    import torch
+
+    rng = np.random.default_rng(23)
+    n = 4000
+    X = rng.uniform(0, 1, (n, 16)).astype(np.float32)
+    mask = (rng.integers(0, 32, n) | 1).astype(np.int32)
+    label = np.array([int(rng.choice(np.flatnonzero((m >> np.arange(5)) & 1))) for m in mask],
+                     np.int32)
+    tx = torch.as_tensor(X, device="cuda")
+    tm = torch.as_tensor(mask, device="cuda")
+    tl = torch.as_tensor(label, device="cuda")
+    kw = dict(batch=1000, lr=3e-3)
+    t_full, l_full = L.train(tx, tm, tl, 5, epochs=4, rng=np.random.default_rng(2), **kw)
+    ck = str(tmp_path / "trainer.ckpt")
+    t_a, l_a = L.train(tx, tm, tl, 5, epochs=2, rng=np.random.default_rng(2), checkpoint=ck, **kw)
+    assert len(l_a) == 2
+    t_b, l_b = L.train(tx, tm, tl, 5, epochs=4, rng=np.random.default_rng(2), checkpoint=ck,
+                       resume=True, **kw)
+    assert l_b == l_full
+    assert bytes(t_b.export()) == bytes(t_full.export())
+    # the saved state round-trips through a fresh trainer
+    st = t_b.state()
+    t_c = V.Trainer(L.init_model(5, np.random.default_rng(3)))
+    t_c.restore(st)
+    assert t_c.state() == st
+    with pytest.raises(V.VsbppError) as e:
+        t_c.restore(b"X" * len(st))
+    assert e.value.code == -9
+    with pytest.raises(V.VsbppError) as e:
+        t_c.restore(st[:-4])
+    assert e.value.code == -2
+    t_d = V.Trainer(L.init_model(3, np.random.default_rng(4)))
+    with pytest.raises(V.VsbppError) as e:
+        t_d.restore(st)
+    assert e.value.code == -2
+    for t in (t_full, t_a, t_b, t_c, t_d):
+        t.close()
+
+
 def test_trained_scorer_gain(V, L):
     """Labels from rollouts on training instances, GPU training, then paired
     evaluation on held-out instances: reports mean cost/LB of the plain rule
