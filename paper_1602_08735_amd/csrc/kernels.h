@@ -93,6 +93,12 @@ inline bool plain_ext(const BatchArgs& a) {
   return a.src || a.force || a.feat_out || a.info_out || a.count_out || a.type_rule == 2 ||
          a.choice_rule == 2;
 }
+// plain runs with the learned bin-type rule alone: no decision hooks, bin
+// choice or bound on the open bins (a lean instantiation of the scorer kernel)
+inline bool plain_lean_learned(const BatchArgs& a) {
+  return a.type_rule == 2 && a.choice_rule == 0 && !a.src && !a.force && !a.feat_out &&
+         !a.info_out && !a.count_out && a.active_limit == 0;
+}
 // plain runs that evaluate the network (bin-type scorer or bin choice)
 __host__ __device__ inline bool plain_scored(const BatchArgs& a) {
   return a.type_rule == 2 || a.choice_rule == 2;

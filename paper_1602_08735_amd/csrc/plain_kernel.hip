@@ -261,10 +261,15 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 // a.active_limit > 0); unbounded plain runs use the instantiation without it.
 // OPT bit 1 (extended runs): the per-bin loads of the downsized cost of
 // entries that name a source instance are kept; other runs go without them.
+// OPT bit 2 (extended runs): the learned bin-type rule alone, with no
+// decision hooks, bin choice or bound on the open bins, whose option checks
+// then fold away.
 template <int CRIT, typename K, bool EXT, bool SPILL, int OPT>
 __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per_wave) {
   constexpr bool BND = (OPT & 1) != 0;
   constexpr bool DSL = EXT && (OPT & 2) != 0;
+  constexpr bool LEAN = EXT && (OPT & 4) != 0;
+  static_assert(!(LEAN && (BND || DSL)), "the lean learned run has no bound and no loads");
   static_assert(!(EXT && SPILL), "decision hooks and the scorer run from LDS");
   using KT = KeyT<K>;
   using Pid = typename KT::Pid;
@@ -318,7 +323,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     if constexpr (SPILL) carve(a.spill + (size_t)inst * (size_t)per_wave);
     K* const mine = keys + 4 * lane;
     // inputs come from instance `src_i` (entries may share an instance)
-    const int src_i = (EXT && a.src) ? uniform(a.src[inst]) : inst;
+    const int src_i = (EXT && !LEAN && a.src) ? uniform(a.src[inst]) : inst;
     const int64_t off = a.item_off[src_i];
     const int64_t m64 = a.item_off[src_i + 1] - off;
     const int c0 = a.cap_off[src_i];
@@ -336,7 +341,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     }
     // the bin choice scores two outputs (keep, open)
     if constexpr (EXT) {
-      if (!err && a.choice_rule == 2 && md->n_out < 2) err = kErrModel;
+      if (!err && !LEAN && a.choice_rule == 2 && md->n_out < 2) err = kErrModel;
     }
     const int m = (int)m64;
     const int nch = (m + 63) >> 6;
@@ -397,7 +402,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     float fg_base = 0.0f;
     int32_t hslot = 7;
     if constexpr (EXT) {
-      if (a.force) {
+      if (!LEAN && a.force) {
         fd = uniform(a.force[3 * (int64_t)inst]);
         ft1 = uniform(a.force[3 * (int64_t)inst + 1]);
         ft2 = uniform(a.force[3 * (int64_t)inst + 2]);
@@ -414,7 +419,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       inv_cap_lane = lane < n ? 1.0f / (float)cap_lane : 0.0f;
       // lane l in 11..14 reads B_{l-10} from lane l - 10 (0 beyond n)
       const int32_t cap_up = __shfl(cap_lane, lane >= 11 && lane <= 14 ? lane - 10 : 0, kWave);
-      if (a.choice_rule == 0 && lane >= 11 && lane <= 14) fa_base = cap_up;
+      if ((LEAN || a.choice_rule == 0) && lane >= 11 && lane <= 14) fa_base = cap_up;
       fg_base = (lane == 1 || lane == 4) ? inv_m : inv_b1;
       if (lane >= 5 && lane <= 10) hslot = lane - 5;
     }
@@ -471,7 +476,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
       int32_t tv = 0, btv = 0, rv = 0;
       uint32_t minroomv = 0xFFFFFFFFu;
       if (runs) {
-        if (a.type_rule != 1)
+        if (LEAN || a.type_rule != 1)
           for (int k = 1; k < n; ++k) tv += readlane(cap_lane, k) >= wv ? 1 : 0;
         btv = __shfl(cap_lane, tv, kWave);
         rv = q < m ? btv - wv : 0;
@@ -619,7 +624,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           // placement into the criterion's bin is contested when c(L + w) >
           // c(L); the capacities are distinct and decreasing, so that is when
           // fewer types hold L + w than hold L.
-          if (a.choice_rule != 0 && p >= 0) {
+          if (!LEAN && a.choice_rule != 0 && p >= 0) {
             const int32_t ra = (int32_t)room_of<CRIT>(nk);  // room after the item
             const int32_t L = B1 - ra - w;
             const uint64_t hb = ballot(cap_lane >= L);
@@ -658,7 +663,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
                   }
                 }
               }
-              if (fd >= 0) {  // forced decisions (rollouts) only
+              if (!LEAN && fd >= 0) {  // forced decisions (rollouts) only
                 const int ft = d == fd ? ft1 : (d == fd + 1 ? ft2 : -1);
                 if (ft == 0 || ft == 1) open = ft == 1;
               }
@@ -715,21 +720,21 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
           // types holding the item (lanes >= n hold capacity 0 and w >= 1)
           const uint64_t fm = ballot(cap_lane >= w);
           const int smallest = (int)__popcll(fm) - 1;
-          int t = a.type_rule == 1 ? 0 : smallest;
+          int t = (!LEAN && a.type_rule == 1) ? 0 : smallest;
           // under the bin choice the decisions are contested placements, and
           // a bin opened because nothing fits has type 0 (largest type rule)
-          if (EXT && a.choice_rule == 0) {
+          if (EXT && (LEAN || a.choice_rule == 0)) {
             const int d = nev;
-            nev = uniform(nev + 1);
-            const bool dump = d == fd && (a.feat_out || a.info_out);
+            if (!LEAN) nev = uniform(nev + 1);
+            const bool dump = !LEAN && d == fd && (a.feat_out || a.info_out);
             // features only where the scorer has a choice (or a dump asks)
-            if ((a.type_rule == 2 && smallest > 0) || dump) {
+            if (((LEAN || a.type_rule == 2) && smallest > 0) || dump) {
               // lanes 11..14: B_2..B_5 over B_1, lane 15: w over B_t
               const float xl = lane_features(
                   [&](int32_t fa) { return writelane(fa, w, 15); },
                   __uint_as_float(readlane(__float_as_uint(inv_cap_lane), smallest)));
               // with one type holding the item the scorer has nothing to choose
-              if (a.type_rule == 2 && smallest > 0) {
+              if ((LEAN || a.type_rule == 2) && smallest > 0) {
                 const float z = mlp_forward_wave(md, mregs, hbuf, lane);
                 const int kmax = min(n, mregs.n_out);
                 // lanes 0..kmax-1 hold the scores; the choice is the lowest
@@ -750,7 +755,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
                 }
               }
             }
-            if (fd >= 0) {  // forced decisions (rollouts) only
+            if (!LEAN && fd >= 0) {  // forced decisions (rollouts) only
               const int ft = d == fd ? ft1 : (d == fd + 1 ? ft2 : -1);
               if (ft >= 0 && ft < n && ((fm >> ft) & 1ull)) t = ft;
             }
@@ -772,7 +777,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
             pid[(p & ~63) + lane] = (Pid)id;
           }
           if (dsl && lane == 0) bload[id] = w;
-          const bool out_types = !EXT || !a.src;
+          const bool out_types = !EXT || LEAN || !a.src;
           if (out_types && lane == 0) a.types[off + id] = t;
           cost += Bt;
           minroom = min(minroom, (uint32_t)room);
@@ -785,7 +790,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
         mypos = writelane(mypos, p, jj);
       }
       if (runs) minroom = min(minroom, wave_min(minroomv));
-      if ((!EXT || !a.src) && q < m) a.assign[off + item] = (int32_t)pid[mypos];
+      if ((!EXT || LEAN || !a.src) && q < m) a.assign[off + item] = (int32_t)pid[mypos];
     }
     if (runs) cost += (Cost)wave_sum64((int64_t)costv);
     int64_t out_cost = cost;
@@ -806,7 +811,7 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, int wpb, int64_t per
     if (lane == 0) {
       a.nbins[inst] = nb;
       a.cost[inst] = out_cost;
-      if (EXT && a.count_out) a.count_out[inst] = nev;
+      if (EXT && !LEAN && a.count_out) a.count_out[inst] = nev;
     }
   }
 }
@@ -831,16 +836,18 @@ hipError_t launch_one(const BatchArgs& a, int wpb, size_t per_wave, int grid, hi
 template <int CRIT, typename K>
 hipError_t launch_sel(const BatchArgs& a, int wpb, size_t per_wave, int grid, hipStream_t s) {
   if (a.spill) return launch_one<CRIT, K, false, true, 1>(a, wpb, per_wave, grid, s);
-  if (plain_ext(a))
+  if (plain_ext(a)) {
+    if (plain_lean_learned(a)) return launch_one<CRIT, K, true, false, 4>(a, wpb, per_wave, grid, s);
     return plain_ds_loads(a) ? launch_one<CRIT, K, true, false, 3>(a, wpb, per_wave, grid, s)
                              : launch_one<CRIT, K, true, false, 1>(a, wpb, per_wave, grid, s);
+  }
   return a.active_limit > 0 ? launch_one<CRIT, K, false, false, 1>(a, wpb, per_wave, grid, s)
                             : launch_one<CRIT, K, false, false, 0>(a, wpb, per_wave, grid, s);
 }
 
 template <int CRIT, typename K>
 int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill, bool bounded,
-              bool dsl) {
+              bool dsl, bool lean) {
   int n = 0;
   hipError_t e;
   if (spill) {
@@ -848,7 +855,10 @@ int occupancy(int wpb, size_t per_wave, bool ext, bool learned, bool spill, bool
                                                      64 * wpb, 0);
   } else {
     const size_t lds = per_wave * (size_t)wpb + (ext ? plain_lds_block_extra(learned) : 0);
-    if (ext && dsl)
+    if (ext && lean)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false, 4>,
+                                                       64 * wpb, lds);
+    else if (ext && dsl)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plain<CRIT, K, true, false, 3>,
                                                        64 * wpb, lds);
     else if (ext)
@@ -896,16 +906,16 @@ hipError_t launch_plain_grid(const BatchArgs& a, int crit, bool wide, int wpb,
 
 int plain_blocks_per_cu(const BatchArgs& a, int crit, bool wide, int wpb, size_t lds_per_wave) {
   const bool ext = plain_ext(a), learned = plain_scored(a), spill = a.spill != nullptr;
-  const bool bnd = a.active_limit > 0, dsl = plain_ds_loads(a);
+  const bool bnd = a.active_limit > 0, dsl = plain_ds_loads(a), lean = plain_lean_learned(a);
   const size_t lw = lds_per_wave;
   if (!wide) {
-    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl);
-    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl);
-    return occupancy<WF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl);
+    if (crit == FF) return occupancy<FF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl, lean);
+    if (crit == BF) return occupancy<BF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl, lean);
+    return occupancy<WF, uint32_t>(wpb, lw, ext, learned, spill, bnd, dsl, lean);
   }
-  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl);
-  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl);
-  return occupancy<WF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl);
+  if (crit == FF) return occupancy<FF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl, lean);
+  if (crit == BF) return occupancy<BF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl, lean);
+  return occupancy<WF, uint64_t>(wpb, lw, ext, learned, spill, bnd, dsl, lean);
 }
 
 }  // namespace vsbpp
