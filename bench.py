@@ -68,10 +68,10 @@ FP32_NONPACKED_PEAK = FP32_PEAK / 2
 # counts half of a known-size copy's reads) and WRITE_SIZE (x1), with the
 # commit the counters were taken at (profiles/).  A launch whose kernel has
 # changed since then reports null.
-MEASURED_HBM_BYTES = {"FF": 51.56e6, "BF": 51.35e6, "WF": 51.33e6, "H1": 47.23e6,
-                      "H2": 47.23e6, "FF+scorer": 48.77e6, "BF+scorer": 48.55e6,
-                      "WF+scorer": 49.74e6}
-MEASURED_HBM_AT = "80d711e"
+MEASURED_HBM_BYTES = {"FF": 51.30e6, "BF": 50.93e6, "WF": 51.46e6, "H1": 47.22e6,
+                      "H2": 47.06e6, "FF+scorer": 48.64e6, "BF+scorer": 48.68e6,
+                      "WF+scorer": 49.56e6}
+MEASURED_HBM_AT = "0036459"
 
 
 # Exact solver leg (outside the step): instances of the uniform distribution
