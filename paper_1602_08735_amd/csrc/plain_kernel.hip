@@ -3,7 +3,8 @@
 //
 // Per item (the hot step): every live bin tests in parallel whether the item
 // fits (Rule 4 applicability) and a wave reduction picks the bin:
-//   FF: ballot over 64-bin rows in position order, first set lane;
+//   FF: min of (position << SH | room) over the fitting bins (the key with
+//       its halves swapped);
 //   BF: min of (room_after << SH | position);
 //   WF: min of ((R - room_after) << SH | position);
 // lowest position wins ties by construction, and positions keep bin-creation
